@@ -1,0 +1,173 @@
+"""ctypes binding of the CPU oracle -- TEST INFRASTRUCTURE, NOT THE PRODUCT PATH.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  It loads ``oracle/liborc.so`` (built by
+``oracle/build.py`` with g++, independent of the HIP library) and exposes:
+
+* :func:`step`      -- advance (phi, c_s, c_l) by n explicit steps
+                       (Eqs. cs_nonvar, cl_nonvar, phasefield_nonvar; Sec. V.A);
+* :func:`jvp`       -- the same steps on dual numbers: exact directional
+                       derivative w.r.t. the fields and theta = (A, M_phi, W);
+* :func:`energy`    -- discrete free energy (Eq. model1.1, dilute alloy Eq. dil_linear);
+* :func:`solute`    -- total solute, max c and its first index (Eq. model1, k_v of Sec. V.C);
+* :func:`pointwise` and :func:`phi_t` -- per-cell quantities for the pins.
+
+Parameters are a plain ``dict`` (see :data:`DEFAULTS`); fields are float64
+numpy arrays in the grid layout (axis 0 fastest, growth axis last).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+#: Default nondimensional parameters (lengths in W0, time in W0^2/D_l, c in c_inf).
+DEFAULTS = dict(
+    dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0,
+    dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=1.2,
+    b=1e-4, ap=0.0, inv_lT=1.0 / 444.0, V=0.1, z0=256 * 0.8, eps_grad=1e-20,
+)
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+        ("quintic", C.c_int32), ("drag_variant", C.c_int32), ("pad_", C.c_int32),
+        ("dx", C.c_double), ("dt", C.c_double), ("W", C.c_double), ("Mphi", C.c_double),
+        ("lambda0", C.c_double), ("Ds", C.c_double), ("ke", C.c_double), ("A", C.c_double),
+        ("b", C.c_double), ("ap", C.c_double), ("inv_lT", C.c_double), ("V", C.c_double),
+        ("z0", C.c_double), ("eps_grad", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the oracle shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"oracle library missing: {LIB_PATH} (run oracle/build.py)")
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_params_size.restype = C.c_int
+        L.orc_step.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_long, C.POINTER(C.c_int64)]
+        L.orc_step.restype = C.c_int
+        L.orc_jvp.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, dp, dp, C.c_long, C.c_long,
+                              C.POINTER(C.c_int64)]
+        L.orc_jvp.restype = C.c_int
+        L.orc_energy.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64]
+        L.orc_energy.restype = C.c_double
+        L.orc_solute.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
+        L.orc_solute.restype = C.c_int
+        L.orc_pointwise.argtypes = [C.POINTER(_Params), C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_pointwise.restype = C.c_int
+        L.orc_phi_t.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64, dp]
+        L.orc_phi_t.restype = C.c_int
+        if L.orc_params_size() != C.sizeof(_Params):
+            raise RuntimeError("oracle parameter layout mismatch")
+        _lib = L
+    return _lib
+
+
+def params(**kw) -> dict:
+    """DEFAULTS updated by keyword arguments."""
+    p = dict(DEFAULTS)
+    unknown = set(kw) - set(p)
+    if unknown:
+        raise KeyError(f"unknown oracle parameters: {sorted(unknown)}")
+    p.update(kw)
+    return p
+
+
+def _cparams(p: dict) -> _Params:
+    s = _Params()
+    s.dim = int(p["dim"])
+    n = list(p["n"]) + [1] * (3 - len(p["n"]))
+    per = list(p["periodic"]) + [0] * (3 - len(p["periodic"]))
+    for k in range(3):
+        s.n[k] = int(n[k])
+        s.periodic[k] = int(per[k])
+    s.quintic = int(p["quintic"])
+    s.drag_variant = int(p["drag_variant"])
+    for f in ("dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b", "ap", "inv_lT", "V", "z0",
+              "eps_grad"):
+        setattr(s, f, float(p[f]))
+    return s
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ncell(p: dict) -> int:
+    n = list(p["n"]) + [1, 1, 1]
+    return int(np.prod([n[k] if k < p["dim"] else 1 for k in range(3)]))
+
+
+def _fields(phi, cs, cl, p):
+    out = []
+    for a in (phi, cs, cl):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64)).copy()
+        if a.size != _ncell(p):
+            raise ValueError("field size does not match the grid")
+        out.append(a)
+    return out
+
+
+def step(p: dict, phi, cs, cl, nsteps: int, n0: int = 0, shift: int = 0):
+    """Advance copies of the fields by ``nsteps`` steps from step index ``n0``.
+
+    Returns ``(phi, cs, cl, shift)`` with ``shift`` the updated window count."""
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    s = C.c_int64(int(shift))
+    rc = lib().orc_step(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n0), int(nsteps), C.byref(s))
+    if rc != 0:
+        raise RuntimeError("orc_step failed")
+    return phi, cs, cl, int(s.value)
+
+
+def jvp(p: dict, phi, cs, cl, dphi, dcs, dcl, dtheta, nsteps: int, n0: int = 0, shift: int = 0):
+    """Dual-number forward mode: returns ``(u_out(3), du_out(3), shift)``."""
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    dphi, dcs, dcl = _fields(dphi, dcs, dcl, p)
+    th = np.ascontiguousarray(np.asarray(dtheta, dtype=np.float64).reshape(3))
+    s = C.c_int64(int(shift))
+    rc = lib().orc_jvp(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), _ptr(dphi), _ptr(dcs),
+                       _ptr(dcl), _ptr(th), int(n0), int(nsteps), C.byref(s))
+    if rc != 0:
+        raise RuntimeError("orc_jvp failed")
+    return (phi, cs, cl), (dphi, dcs, dcl), int(s.value)
+
+
+def energy(p: dict, phi, cs, cl, n: int = 0, shift: int = 0) -> float:
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    return float(lib().orc_energy(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n), int(shift)))
+
+
+def solute(p: dict, phi, cs, cl):
+    """Returns ``(total, cmax, argmax)``."""
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    tot, cm, am = C.c_double(), C.c_double(), C.c_long()
+    lib().orc_solute(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), C.byref(tot), C.byref(cm), C.byref(am))
+    return float(tot.value), float(cm.value), int(am.value)
+
+
+def pointwise(p: dict, phi: float, cs: float, cl: float, cleq: float) -> dict:
+    out = np.zeros(7)
+    lib().orc_pointwise(C.byref(_cparams(p)), float(phi), float(cs), float(cl), float(cleq), _ptr(out))
+    keys = ("h", "p", "dp", "dfdw", "dmu", "mubar", "dG")
+    return dict(zip(keys, out.tolist()))
+
+
+def phi_t(p: dict, phi, cs, cl, n: int = 0, shift: int = 0) -> np.ndarray:
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    out = np.zeros_like(phi)
+    lib().orc_phi_t(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n), int(shift), _ptr(out))
+    return out

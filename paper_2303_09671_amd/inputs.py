@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs (shared by the tests, the smoke check and the benchmark).
+
+This module builds initial states and run tables only; it contains none of the
+time-stepping arithmetic.  Both the HIP path and the CPU oracle receive the
+arrays it returns.  Every random number is drawn here from numpy's PCG64 with a
+fixed seed and handed to both sides as data.
+
+Recipe (nondimensional: lengths in W0, time in W0^2/D_l, c in c_inf):
+
+* planar front at height ``z0`` (a cell face) on the growth axis, the last
+  axis: phi0 = 1 / (1 + exp(sqrt(2) (z - z0) / W)), the equilibrium profile of
+  the supplement (Sec. S-I, Eq. eq18) written in logistic form;
+* homogeneous phase concentrations c_l = c_inf = 1, c_s = k_e (Sec. V.A);
+* optional seeded perturbation phi += amp (2 xi - 1) 4 phi0 (1 - phi0),
+  xi ~ U[0, 1), band-limited to the interface so the bulk stays exactly 0/1;
+* the five workload definitions of the hot path (1D front, 2D and 3D
+  directional solidification, a 256-run k(V) sweep, the adjoint fit runs).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+#: Alloy and model parameters shared by every workload (nondimensional).
+ALLOY = dict(
+    ke=0.14,            # equilibrium partition coefficient
+    Ds=1e-4,            # D_s / D_l
+    W=1.0,              # interface width / W0
+    Mphi=1.0,           # phi mobility: alpha = tau D_l / W0^2 = W / Mphi
+    lambda0=0.04462,    # Omega c_inf / H at W = W0 (I (W/d0) k_e / (1-k_e)^2 with W/d0 = 1)
+    A=1.2,              # source / trapping coefficient
+    b=1e-4, ap=0.0,     # interpolation set 2 constants: b = D_s/D_l (symmetric q_n), a_p = 0
+    quintic=1,
+    inv_lT=1.0 / 444.0, # 1 / thermal length l_T = dT0 / G
+    eps_grad=1e-20,     # gate on |grad phi|^2
+)
+
+DX = 0.8
+
+
+def grid_shape(dim: int, n) -> tuple:
+    """numpy shape (slowest first) for cells-per-axis ``n`` (axis 0 fastest)."""
+    n = tuple(int(v) for v in n)[:dim]
+    return tuple(reversed(n))
+
+
+def planar_front(dim: int, n, dx: float, z0: float, ke: float, W: float = 1.0,
+                 amp: float = 0.0, seed: int | None = None):
+    """Initial (phi, c_s, c_l) as float64 arrays of shape ``grid_shape(dim, n)``."""
+    shape = grid_shape(dim, n)
+    nz = shape[0]
+    z = (np.arange(nz, dtype=np.float64) + 0.5) * dx
+    arg = math.sqrt(2.0) * (z - z0) / W
+    with np.errstate(over="ignore"):
+        phi1 = 1.0 / (1.0 + np.exp(arg))
+    phi = np.broadcast_to(phi1.reshape((nz,) + (1,) * (dim - 1)), shape).copy()
+    if amp != 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        xi = rng.random(shape)
+        phi = phi + amp * (2.0 * xi - 1.0) * 4.0 * phi * (1.0 - phi)
+    cs = np.full(shape, ke, dtype=np.float64)
+    cl = np.ones(shape, dtype=np.float64)
+    return phi, cs, cl
+
+
+def base_params(**kw) -> dict:
+    p = dict(ALLOY)
+    p.update(dict(dx=DX, V=0.1, dt=0.128, z0=0.0, dim=1, n=(1, 1, 1), periodic=(0, 0, 0)))
+    p.update(kw)
+    return p
+
+
+def config_1d(N: int = 1024, steps: int = 20000):
+    """1D planar rapid-solidification front: N=1024, dx=0.8 W, V=0.1,
+    dt = 0.2 dx^2, 20000 steps, front at N/4, no-flux ends."""
+    p = base_params(dim=1, n=(N, 1, 1), V=0.1, dt=0.2 * DX * DX, z0=(N // 4) * DX)
+    return p, steps
+
+
+def config_2d(nx: int = 1024, nz: int = 1024, steps: int = 10000, seed: int = 1, amp: float = 1e-3):
+    """2D directional solidification: periodic x, no-flux z, V=0.05,
+    dt = 0.2 dx^2 / 4, seeded front perturbation of amplitude 1e-3."""
+    p = base_params(dim=2, n=(nx, nz, 1), periodic=(1, 0, 0), V=0.05, dt=0.2 * DX * DX / 4.0,
+                    z0=(nz // 4) * DX)
+    return p, steps, dict(amp=amp, seed=seed)
+
+
+def config_3d(n: int = 256, steps: int = 2000, seed: int = 2, amp: float = 1e-3):
+    """3D directional solidification, 256^3, x and y periodic, same alloy as 2D."""
+    p = base_params(dim=3, n=(n, n, n), periodic=(1, 1, 0), V=0.05, dt=0.2 * DX * DX / 4.0,
+                    z0=(n // 4) * DX)
+    return p, steps, dict(amp=amp, seed=seed)
+
+
+def run_dt(V: float, dx: float = DX, alpha: float = 1.0, W: float = 1.0) -> float:
+    """Per-run time step from the run's stability limits (diffusion, window
+    advection, phi relaxation)."""
+    return min(0.2 * dx * dx, 0.1 * dx / V, 0.4 * alpha * dx * dx / (2.0 * W * W))
+
+
+def batch_runs(nruns: int = 256, seed: int = 3, nmin: int = 512, nmax: int = 8192,
+               vmin_log10: float = -3.0, vmax_log10: float = 1.0):
+    """k(V) sweep: velocities log-spaced from 1e-3 to 10, lengths uniform in
+    [512, 8192] (seeded), per-run dt from ``run_dt``, front at N/4.
+
+    Returns a list of dicts with keys N, V, dt, z0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xi = rng.random(nruns)
+    runs = []
+    for r in range(nruns):
+        frac = r / (nruns - 1) if nruns > 1 else 0.0
+        V = 10.0 ** (vmin_log10 + (vmax_log10 - vmin_log10) * frac)
+        N = nmin + int(math.floor((nmax - nmin + 1) * xi[r]))
+        runs.append(dict(N=N, V=V, dt=run_dt(V), z0=(N // 4) * DX))
+    return runs
+
+
+def adjoint_runs(nruns: int = 64, N: int = 2048, seed: int = 4):
+    """Adjoint fit workload: 64 runs of N=2048 with V log-spaced 1e-2..1 and a
+    seeded target k*(V) = (k_e + V/V_D) / (1 + V/V_D), V_D ~ U[0.1, 1]."""
+    runs = batch_runs(nruns=nruns, seed=0, nmin=N, nmax=N, vmin_log10=-2.0, vmax_log10=0.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    VD = 0.1 + 0.9 * rng.random()
+    ke = ALLOY["ke"]
+    for r in runs:
+        r["N"] = N
+        r["z0"] = (N // 4) * DX
+        r["k_target"] = (ke + r["V"] / VD) / (1.0 + r["V"] / VD)
+    return runs, VD
+
+
+def batch_fields(runs, ke: float = ALLOY["ke"], W: float = 1.0, align: int = 32):
+    """Concatenate the runs' 1D initial states with offsets aligned to ``align``
+    cells (256 B).  Returns (phi, cs, cl, offsets)."""
+    offs = []
+    tot = 0
+    for r in runs:
+        offs.append(tot)
+        tot += (r["N"] + align - 1) // align * align
+    phi = np.zeros(tot)
+    cs = np.full(tot, ke)
+    cl = np.ones(tot)
+    for r, o in zip(runs, offs):
+        f, s, l = planar_front(1, (r["N"],), DX, r["z0"], ke, W)
+        phi[o:o + r["N"]] = f
+        cs[o:o + r["N"]] = s
+        cl[o:o + r["N"]] = l
+    return phi, cs, cl, np.asarray(offs, dtype=np.int64)

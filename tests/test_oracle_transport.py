@@ -1,0 +1,116 @@
+"""Pins of the oracle's transport against closed forms.
+
+* Single-phase bulk diffusion is the textbook explicit (FTCS) heat equation:
+  with phi = 0 (liquid) or 1 (solid) the normal projection vanishes, the flux
+  is D grad c (M grad mu = D grad c for the dilute alloy), and a discrete
+  cosine mode of wavenumber k decays per step by exactly
+  1 - 4 D dt/dx^2 sin^2(k dx/2) per axis (supplement Sec. S-III: Fick's law in
+  the outer region).  Checked for c_s and c_l in 1D (mirror ends), 2D
+  (periodic x) and 3D (periodic x, y), liquid and solid.
+* Single-phase solute is conserved to rounding; two-phase isothermal closed
+  runs conserve total solute up to a drift that shrinks with dt (Eq. model5).
+* Stationary planar front ahead-of-front decay exp(-V z / D_l) and the
+  trapping limit k(V -> 0) -> k_e (Sec. V.C): slow steady fronts started from
+  the sharp-interface profile.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2303_09671_amd import inputs as I
+
+
+def _mode(dim, n, dx, per, m):
+    """Cosine mode: Neumann eigenvector on mirror axes, Fourier on periodic."""
+    coords = np.meshgrid(*[(np.arange(n[k]) + 0.5) * dx for k in range(dim)], indexing="ij")
+    f = np.ones_like(coords[0])
+    ks = []
+    for k in range(dim):
+        L = n[k] * dx
+        kk = (2 * math.pi * m[k] / L) if per[k] else (math.pi * m[k] / L)
+        f = f * np.cos(kk * coords[k])
+        ks.append(kk)
+    # numpy axis 0 is the slowest in memory -> transpose to (axis dim-1 ... axis 0)
+    return np.ascontiguousarray(f.transpose(tuple(range(dim - 1, -1, -1)))).ravel(), ks
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("phase", [0.0, 1.0])
+def test_bulk_ftcs_amplification(oracle, dim, phase):
+    n = {1: (24, 1, 1), 2: (12, 10, 1), 3: (8, 6, 10)}[dim]
+    per = {1: (0, 0, 0), 2: (1, 0, 0), 3: (1, 1, 0)}[dim]
+    m = {1: (3,), 2: (2, 3), 3: (1, 2, 3)}[dim]
+    dx, dt, Ds = 0.8, 0.05, 0.3
+    P = oracle.params(dim=dim, n=n, periodic=per, dx=dx, dt=dt, Ds=Ds, V=0.0, inv_lT=0.0, A=1.7)
+    mode, ks = _mode(dim, n, dx, per, m)
+    N = mode.size
+    phi = np.full(N, phase)
+    cl = 1.0 + 1e-3 * mode
+    cs = 0.3 * (1.0 - 2e-3 * mode)
+    steps = 7
+    phi2, cs2, cl2, _ = oracle.step(P, phi, cs, cl, steps)
+    for D, c0, c2, base, amp in ((1.0, cl, cl2, 1.0, 1e-3), (Ds, cs, cs2, 0.3, -0.6e-3)):
+        lam = 1.0 - sum(4 * D * dt / dx ** 2 * math.sin(k * dx / 2) ** 2 for k in ks)
+        expect = base + amp * lam ** steps * mode
+        assert np.max(np.abs(c2 - expect)) < 1e-14
+    assert np.array_equal(phi2, phi)
+
+
+def test_single_phase_conservation_exact(oracle):
+    P = oracle.params(dim=2, n=(10, 12, 1), periodic=(1, 0, 0), V=0.0, inv_lT=0.0, dt=0.05)
+    rng = np.random.default_rng(3)
+    N = 120
+    phi = np.zeros(N)
+    cl = 1.0 + 0.2 * rng.random(N)
+    cs = 0.2 + 0.05 * rng.random(N)
+    t0, _, _ = oracle.solute(P, phi, cs, cl)
+    phi2, cs2, cl2, _ = oracle.step(P, phi, cs, cl, 50)
+    t1, _, _ = oracle.solute(P, phi2, cs2, cl2)
+    assert abs(t1 - t0) < 1e-12 * abs(t0)
+
+
+def test_two_phase_conservation_converges(oracle):
+    """The discrete scheme conserves c = p c_s + (1-p) c_l only up to its
+    truncation error; the drift over t = 16 shrinks under refinement
+    (dt = 0.05 dx^2), by at least 3x per halving of dx."""
+    drifts = []
+    for dx in (0.8, 0.4, 0.2):
+        dt = 0.05 * dx * dx
+        N = int(round(160.0 / dx))
+        P = oracle.params(dim=1, n=(N, 1, 1), V=0.0, inv_lT=0.0, z0=64.0, dt=dt, dx=dx)
+        phi, cs, cl = I.planar_front(1, (N,), dx, 64.0, P["ke"])
+        t0, _, _ = oracle.solute(P, phi, cs, cl)
+        phi2, cs2, cl2, _ = oracle.step(P, phi, cs, cl, int(round(16.0 / dt)))
+        t1, _, _ = oracle.solute(P, phi2, cs2, cl2)
+        drifts.append(abs(t1 - t0) / t0)
+    assert drifts[0] < 1e-3
+    assert drifts[1] < drifts[0] / 3 and drifts[2] < drifts[1] / 3
+
+
+def _steady_front(oracle, V, N=1200, steps=20000):
+    ke, dx = 0.14, 0.8
+    zi = 200 * dx
+    P = oracle.params(dim=1, n=(N, 1, 1), V=V, dt=0.128, z0=zi)
+    z = (np.arange(N) + 0.5) * dx
+    with np.errstate(over="ignore"):
+        phi = 1.0 / (1.0 + np.exp(math.sqrt(2.0) * (z - zi)))
+    cl = np.where(z > zi, 1.0 + (1.0 - ke) / ke * np.exp(-V * (z - zi)), 1.0 / ke)
+    cs = ke * cl
+    phi, cs, cl, _ = oracle.step(P, phi, cs, cl, steps)
+    _, cmax, am = oracle.solute(P, phi, cs, cl)
+    i0, i1 = am + 40, am + 200
+    slope = np.polyfit(z[i0:i1], np.log(cl[i0:i1] - 1.0), 1)[0]
+    return 1.0 / cmax, slope
+
+
+def test_trapping_limit_and_far_field():
+    from oracle import oracle as O
+    k1, s1 = _steady_front(O, 0.0025)
+    k2, s2 = _steady_front(O, 0.005)
+    ke = 0.14
+    assert ke < k1 < k2 < 0.16                     # trapping grows with V
+    k0 = k1 - (k2 - k1)                            # linear extrapolation to V = 0
+    assert abs(k0 - ke) < 2e-3
+    for V, s in ((0.0025, s1), (0.005, s2)):       # c_l - c_inf ~ exp(-V z / D_l)
+        assert s == pytest.approx(-V, rel=0.05)
