@@ -1,0 +1,216 @@
+"""Benchmark of the hot path on one MI355X.
+
+One bench step = one explicit forward-Euler step of the 3D directional-
+solidification workload (256^3 cells, FP64, fields phi, c_s, c_l) through the
+C ABI (pf_step), with the diagnostics (pf_energy, pf_solute) every 100 steps
+inside the timed region.  Inputs are seeded, synthetic and resident in HBM
+before timing starts.  Prints ONE JSON line:
+
+* value      -- whole-job FP64 cell-updates per second (cells x steps / time);
+* roofline   -- the fused step kernel against the HBM roofline: algorithmic
+                48 B per cell-update (read and write phi, c_s, c_l) divided by
+                the kernel's average duration from HIP events on the launch
+                stream; traffic from committed rocprofv3 FETCH/WRITE counters
+                (profiles/) when they were taken on the current kernel source;
+* cpu_baseline -- the CPU oracle on a bounded sample (one step of the same
+                256^3 grid), single thread;
+* extra      -- the other workloads of the hot path: 2D 1024^2, the 1D front,
+                the batched 256-run k(V) sweep against 256 sequential launches,
+                and (when built) the adjoint/forward step-time ratio.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = 48.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream3d_256_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_09671_amd", "csrc", f) for f in ("pf_device.h", "pf_kernels.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def time_domain(torch, pf, p, pert, steps, warmup, diag_every=100):
+    """Returns (total_s, kernel_s, cells, handle, fields)."""
+    from paper_2303_09671_amd import inputs as I
+    f = I.planar_front(p["dim"], p["n"], p["dx"], p["z0"], p["ke"], amp=pert["amp"], seed=pert["seed"])
+    t = [dev(torch, a) for a in f]
+    h = pf.pf_create(p, *t)
+    cells = int(np.prod([p["n"][k] for k in range(p["dim"])]))
+    if warmup:
+        pf.pf_step(h, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    pairs = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        m = min(diag_every, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pf.pf_step(h, m)
+        b.record(stream)
+        pairs.append((a, b))
+        done += m
+        pf.pf_energy(h)
+        pf.pf_solute(h)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    kern = sum(a.elapsed_time(b) for a, b in pairs) / 1e3
+    return total, kern, cells, h, t
+
+
+def bench_batch(torch, pf, steps):
+    """256-run k(V) sweep: one persistent launch vs 256 sequential single-run launches."""
+    from paper_2303_09671_amd import inputs as I
+    runs = I.batch_runs()
+    base = I.base_params(dim=1)
+    phi, cs, cl, offs = I.batch_fields(runs)
+    t = [dev(torch, a) for a in (phi, cs, cl)]
+    h = pf.pf_create(base, *t, runs=runs, offsets=offs)
+    pf.pf_step(h, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pf.pf_step(h, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # sequential: one handle per run, launched one after the other
+    hs = []
+    for r, o in zip(runs, offs):
+        tt = [x[o:o + r["N"]] for x in t]
+        pr = dict(base, dim=1, n=(r["N"], 1, 1), V=r["V"], dt=r["dt"], z0=r["z0"])
+        hs.append(pf.pf_create(pr, *tt))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for hh in hs:
+        pf.pf_step(hh, steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    cells = sum(r["N"] for r in runs)
+    return dict(runs=len(runs), steps_each=steps, cells_total=cells, persistent_s=t_batch, sequential_s=t_seq,
+                speedup=t_seq / t_batch, cell_updates_per_s=cells * steps / t_batch)
+
+
+def cpu_baseline(p, pert):
+    from oracle import oracle as O
+    from paper_2303_09671_amd import inputs as I
+    keys = ("dim", "n", "periodic", "quintic", "dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b", "ap",
+            "inv_lT", "V", "z0", "eps_grad")
+    po = O.params(**{k: p[k] for k in keys})
+    f = [a.ravel() for a in I.planar_front(p["dim"], p["n"], p["dx"], p["z0"], p["ke"], amp=pert["amp"],
+                                           seed=pert["seed"])]
+    cells = int(np.prod([p["n"][k] for k in range(p["dim"])]))
+    t0 = time.perf_counter()
+    O.step(po, *f, 1)
+    dt = time.perf_counter() - t0
+    return dict(value=cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"one step of the full {'x'.join(str(v) for v in p['n'][:p['dim']])} grid "
+                       f"({cells} cell-updates, {dt:.1f} s, single thread)")
+
+
+def traffic_entry():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    d = json.load(open(TRAFFIC_FILE))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device copy of known size (for scaling the FETCH/WRITE counters)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true", help="time only the 3D workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true", help="run the plain copy used to scale counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration()
+        return
+    import torch
+    from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd import pf
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pf.lib()
+
+    p3, _, pert3 = I.config_3d()
+    total, kern, cells, h, _ = time_domain(torch, pf, p3, pert3, args.steps, args.warmup)
+    value = cells * args.steps / total
+    k_avg = kern / args.steps
+    achieved = BYTES_PER_CELL * cells / k_avg / 1e9
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=traffic_entry(), kernel="k_stream<3,32,8>", kernel_avg_us=k_avg * 1e6,
+                algorithmic_bytes_per_launch=BYTES_PER_CELL * cells)
+    out = {
+        "metric": "FP64 cell-updates/s and % HBM roofline; adjoint/forward step time ratio",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D directional solidification, 256^3 cells, x/y periodic, no-flux z, V=0.05, "
+                               "dt=0.032, seeded 1e-3 front perturbation; diagnostics every 100 steps",
+                   "cells": cells, "parallelism": "single GPU"},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p3, pert3)
+    if not args.no_extra:
+        extra = {}
+        p2, _, pert2 = I.config_2d()
+        t2, k2, c2, _, _ = time_domain(torch, pf, p2, pert2, 1000, 20)
+        extra["2d_1024x1024"] = dict(cell_updates_per_s=c2 * 1000 / t2, kernel_avg_us=k2 / 1000 * 1e6,
+                                     effective_GBs=BYTES_PER_CELL * c2 / (k2 / 1000) / 1e9)
+        p1, steps1 = I.config_1d()
+        f1 = I.planar_front(1, p1["n"], p1["dx"], p1["z0"], p1["ke"])
+        t1 = [dev(torch, a) for a in f1]
+        h1 = pf.pf_create(p1, *t1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pf.pf_step(h1, steps1)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t0
+        _, cm, _ = pf.pf_solute(h1)
+        extra["1d_1024_20000_steps"] = dict(seconds=d1, cell_updates_per_s=1024 * steps1 / d1, k=float(1.0 / cm[0]))
+        extra["batch_256_runs"] = bench_batch(torch, pf, 2000)
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

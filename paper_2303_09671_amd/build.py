@@ -1,0 +1,35 @@
+"""Build the HIP library libpf.so for gfx950 (hipcc, in-tree).
+
+Flags: -O3, FP64 arithmetic as written (no fast-math), packed FP32 disabled,
+code object for gfx950 only.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "pf_lib.hip")
+OUT = os.path.join(HERE, "libpf.so")
+HEADERS = [os.path.join(ROOT, "include", "pf.h")] + [
+    os.path.join(HERE, "csrc", f) for f in ("pf_device.h", "pf_kernels.h", "pf_adjoint.h")]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+           "-o", OUT + ".tmp", SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(OUT + ".tmp", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

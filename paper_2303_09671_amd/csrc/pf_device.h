@@ -1,0 +1,158 @@
+// pf_device.h -- device-side arithmetic of one explicit step (gfx950, FP64).
+//
+// The per-cell and per-face formulas of the staggered scheme for the set-2
+// equations of motion (Sec. II: Eqs. cs_nonvar, cl_nonvar, phasefield_nonvar,
+// drive of Eq. model18 reduced to dG_c - D (c_s - c_l)(mu_s - mu_l); Sec. III:
+// dilute ideal alloy, Eqs. dil5.2, ds3; Sec. V.A: central gradients at cells,
+// compact normal differences at faces, face-mean mobilities and anti-trapping).
+// Shared by the forward kernels, the persistent 1D kernel and the adjoint.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// Derived constants of a handle, passed by value to every kernel.
+struct Const {
+  // grid: growth axis = z (last axis); x fastest; unused axes have extent 1
+  int dim, nx, ny, nz;
+  int px, py;      // periodic flags of x and y
+  int quintic, pad_;
+  long long ncell;
+  // model
+  double dx, inv_dx, inv_2dx, inv_dx2, dt;
+  double W, W2, alpha, lambda, lambda0, Mphi;
+  double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad;
+};
+
+// Interpolation p(phi) = h + a_p (phi - 1/2) phi^2 (1-phi)^2 (Eq. interpolation2),
+// its complement q = 1 - p evaluated as p(1 - phi) (antisymmetry of p; avoids the
+// cancellation of 1 - p near phi = 1), and p'(phi).
+__device__ __forceinline__ void interp(const Const& c, double phi, double& p, double& q, double& dp) {
+  const double om = 1.0 - phi;
+  const double w = phi * om;
+  double h, hq, dh;
+  if (c.quintic) {
+    h = phi * phi * phi * (phi * (6.0 * phi - 15.0) + 10.0);
+    hq = om * om * om * (om * (6.0 * om - 15.0) + 10.0);
+    dh = 30.0 * w * w;
+  } else {
+    h = phi * phi * (3.0 - 2.0 * phi);
+    hq = om * om * (3.0 - 2.0 * om);
+    dh = 6.0 * w;
+  }
+  const double a = c.ap * (phi - 0.5) * w * w;
+  p = h + a;
+  q = hq - a;
+  const double tt = 1.0 - 2.0 * phi;
+  dp = dh + c.ap * w * (w - tt * tt);
+}
+
+__device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p, double& q) {
+  const double om = 1.0 - phi;
+  const double w = phi * om;
+  double h, hq;
+  if (c.quintic) {
+    h = phi * phi * phi * (phi * (6.0 * phi - 15.0) + 10.0);
+    hq = om * om * om * (om * (6.0 * om - 15.0) + 10.0);
+  } else {
+    h = phi * phi * (3.0 - 2.0 * phi);
+    hq = om * om * (3.0 - 2.0 * om);
+  }
+  const double a = c.ap * (phi - 0.5) * w * w;
+  p = h + a;
+  q = hq - a;
+}
+
+// Equilibrium liquid concentration of the frozen temperature field at lab
+// height zlab and time t (Eqs. dil7, ds1, reference (c_inf, T_s) at z0).
+__device__ __forceinline__ double cleq_at(const Const& c, double zlab, double t, double V, double z0) {
+  return (1.0 - (1.0 - c.ke) * (zlab - z0 - V * t) * c.inv_lT) / c.ke;
+}
+
+// mu_bar = p mu_s + (1-p) mu_l (units of Omega, up to a constant) of one cell.
+__device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs, double cl) {
+  double p, q;
+  interp_pq(c, phi, p, q);
+  const double ll = log(cl);
+  return ll + p * (log(cs) - ll - c.log_ke);
+}
+
+// Cell stage: phi_t (Eq. phasefield_nonvar divided by H) and mu_bar.
+//   g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
+//   compact Laplacian of phi.
+template <int DIM>
+__device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
+                                           const double* gph, const double* gcs, const double* gcl,
+                                           double lap, double& phit, double& mubar) {
+  double p, q, dp;
+  interp(c, phi, p, q, dp);
+  const double ll = log(cl);
+  const double dmu = log(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
+  mubar = ll + p * dmu;
+  const double dc = cs - cl;
+  const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;  // Eq. dil5.2 with Eq. ds3
+  const double ms = c.Ds * cs * q;                          // M_s (1 - p)
+  const double ml = c.b * cl * p;                           // b M_l p
+  const double iM = 1.0 / (ms + ml);                        // 1 / Mbar
+  const double drag = (ms * (1.0 - c.A * q) + c.A * ml * p) * iM;
+  const double dG = dGc - drag * dc * dmu;
+  double G = 0.0, dot = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    G += gph[k] * gph[k];
+    dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
+  }
+  const double gam = (G > c.eps_grad) ? 1.0 / G : 0.0;
+  const double pq = p * q;
+  const double lAdc = c.lambda * c.onemA * dc;
+  const double tau = c.alpha + lAdc * c.onemA * dc * c.b * pq * gam * iM / (c.b * p + q);
+  const double X = lAdc * pq * iM * dot * gam;
+  const double fdw = 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
+  phit = (c.W2 * lap - fdw - c.lambda * dG * dp + X) / tau;
+}
+
+// Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
+// through a face normal to axis k.  phf, csf, clf, ptf are the face means;
+// g*[j] the face gradient (compact along k, mean of central differences
+// across k) of phi, mu_bar, c_s, c_l.
+template <int DIM>
+__device__ __forceinline__ void face_flux(const Const& c, int k, double phf, double csf, double clf,
+                                          double ptf, const double* gph, const double* gmu,
+                                          const double* gcs, const double* gcl, double& Fs,
+                                          double& Fl) {
+  double p, q;
+  interp_pq(c, phf, p, q);
+  double G = 0.0, dmu = 0.0, dcs = 0.0, dcl = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    G += gph[j] * gph[j];
+    dmu += gph[j] * gmu[j];
+    dcs += gph[j] * gcs[j];
+    dcl += gph[j] * gcl[j];
+  }
+  const double gam = (G > c.eps_grad) ? 1.0 / G : 0.0;
+  const double gk = gph[k] * gam;
+  const double Ms = c.Ds * csf;
+  const double Ml = clf;
+  const double ms = Ms * q, ml = c.b * Ml * p;
+  const double iM = 1.0 / (ms + ml);
+  const double qn = Ms * Ml * (c.b * p + q) * iM;
+  const double nrm = qn * dmu * gk;                       // q_n (n n^T grad mu_bar)_k
+  const double at = c.onemA * (csf - clf) * gk * ptf * iM;  // anti-trapping / Mbar
+  Fs = nrm + c.Ds * (gcs[k] - dcs * gk) + at * ms;
+  Fl = nrm + (gcl[k] - dcl * gk) - at * ml;
+}
+
+// Error word bits.
+enum : int { ERR_NONFINITE = 1, ERR_NEGCONC = 2 };
+
+__device__ __forceinline__ int check_bits(double phi, double cs, double cl) {
+  int e = 0;
+  if (!__builtin_isfinite(phi) || !__builtin_isfinite(cs) || !__builtin_isfinite(cl)) e |= ERR_NONFINITE;
+  else if (!(cs > 0.0) || !(cl > 0.0)) e |= ERR_NEGCONC;
+  return e;
+}
+
+}  // namespace pfk

@@ -1,0 +1,727 @@
+// pf_kernels.h -- forward kernels: fused z-streaming step (2D/3D), persistent
+// register-chunk kernel for single and batched 1D runs, deterministic
+// reductions (energy, solute, c_max) and the k_v adjoint seed.
+#pragma once
+
+#include "pf_device.h"
+
+namespace pfk {
+
+// ---------------------------------------------------------------------------
+// Index helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int mirror_idx(int g, int n) {
+  // reflect about the outer faces: -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2
+  while (g < 0 || g >= n) {
+    if (g < 0) g = -g - 1;
+    if (g >= n) g = 2 * n - g - 1;
+  }
+  return g;
+}
+__device__ __forceinline__ int map_axis(int g, int n, int periodic) {
+  if (periodic) {
+    g %= n;
+    return g < 0 ? g + n : g;
+  }
+  return mirror_idx(g, n);
+}
+
+// ---------------------------------------------------------------------------
+// Fused step for 2D and 3D: each workgroup owns a TX x TY column tile of the
+// transverse plane(s) and streams through a range of z planes.  A 4-plane ring
+// of (phi, c_s, c_l) with an in-plane halo of 2 lives in LDS; phi_t and mu_bar
+// of each plane are computed once on the tile plus an in-plane halo of 1 and
+// kept in 2- and 3-plane rings; x/y face fluxes go through LDS and the z-face
+// flux below a cell stays in a register for the next plane.  One HBM read and
+// one HBM write of the three fields per cell and step (plus halo re-reads that
+// hit L2).  With a window shift the updated plane z is stored at z-1 and the
+// fresh liquid layer at the top.
+// ---------------------------------------------------------------------------
+template <int DIM, int TX, int TY>
+struct StreamGeom {
+  static constexpr int NT = TX * TY;
+  static constexpr int BX2 = TX + 4;
+  static constexpr int BY2 = (DIM == 3) ? TY + 4 : 1;
+  static constexpr int BX1 = TX + 2;
+  static constexpr int BY1 = (DIM == 3) ? TY + 2 : 1;
+  static constexpr int P2 = BX2 * BY2;
+  static constexpr int P1 = BX1 * BY1;
+  static constexpr int OY2 = (DIM == 3) ? 2 : 0;
+  static constexpr int OY1 = (DIM == 3) ? 1 : 0;
+  static constexpr int NFX = (TX + 1) * TY;
+  static constexpr int NFY = (DIM == 3) ? TX * (TY + 1) : 0;
+  __device__ static __forceinline__ int i2(int lx, int ly) { return (lx + 2) + BX2 * (ly + OY2); }
+  __device__ static __forceinline__ int i1(int lx, int ly) { return (lx + 1) + BX1 * (ly + OY1); }
+};
+
+template <int DIM, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __restrict__ iph,
+                                                    const double* __restrict__ ics,
+                                                    const double* __restrict__ icl,
+                                                    double* __restrict__ oph, double* __restrict__ ocs,
+                                                    double* __restrict__ ocl, int zchunk, double t_n,
+                                                    double s_n, int do_shift, int* __restrict__ err) {
+  using G = StreamGeom<DIM, TX, TY>;
+  __shared__ double su[4][3][G::P2];
+  __shared__ double spt[2][G::P1];
+  __shared__ double smu[3][G::P1];
+  __shared__ double sfx[2][G::NFX];
+  __shared__ double sfy[2][(G::NFY > 0) ? G::NFY : 1];
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX;
+  const int y0 = blockIdx.y * TY;
+  const int zb = blockIdx.z * zchunk;
+  const int ze = min(zb + zchunk, c.nz);
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const long long plane = (long long)nx * ny;
+  const int ox = tid % TX, oy = tid / TX;  // own column
+  const int gxo = x0 + ox, gyo = y0 + oy;
+  const bool own_valid = (gxo < nx) && (gyo < ny);
+
+  auto load_plane = [&](int gz) {
+    const int slot = (gz + 8) & 3;
+    const int zm = mirror_idx(gz, nz);
+    for (int i = tid; i < G::P2; i += G::NT) {
+      const int lx = i % G::BX2 - 2;
+      const int ly = i / G::BX2 - G::OY2;
+      const int gx = map_axis(x0 + lx, nx, c.px);
+      const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
+      const long long idx = (long long)gx + (long long)nx * gy + plane * zm;
+      su[slot][0][i] = iph[idx];
+      su[slot][1][i] = ics[idx];
+      su[slot][2][i] = icl[idx];
+    }
+  };
+
+  // phi_t and mu_bar of plane gz on the tile plus in-plane halo 1.
+  auto cell_plane = [&](int gz) {
+    const int s0 = (gz + 8) & 3, sm = (gz + 7) & 3, sp = (gz + 9) & 3;
+    const int pt = (gz + 8) & 1, mu = (gz + 9) % 3;
+    const double zlab = ((double)gz + s_n + 0.5) * c.dx;
+    const double cleq = cleq_at(c, zlab, t_n, c.V, c.z0);
+    for (int i = tid; i < G::P1; i += G::NT) {
+      const int lx = i % G::BX1 - 1;
+      const int ly = i / G::BX1 - G::OY1;
+      const int ic = G::i2(lx, ly);
+      double gph[DIM], gcs[DIM], gcl[DIM];
+      const double* U0 = su[s0][0];
+      const double* S0 = su[s0][1];
+      const double* L0 = su[s0][2];
+      const double ph = U0[ic], cs = S0[ic], cl = L0[ic];
+      gph[0] = (U0[ic + 1] - U0[ic - 1]) * c.inv_2dx;
+      gcs[0] = (S0[ic + 1] - S0[ic - 1]) * c.inv_2dx;
+      gcl[0] = (L0[ic + 1] - L0[ic - 1]) * c.inv_2dx;
+      double lap = (U0[ic + 1] - 2.0 * ph + U0[ic - 1]);
+      if (DIM == 3) {
+        gph[1] = (U0[ic + G::BX2] - U0[ic - G::BX2]) * c.inv_2dx;
+        gcs[1] = (S0[ic + G::BX2] - S0[ic - G::BX2]) * c.inv_2dx;
+        gcl[1] = (L0[ic + G::BX2] - L0[ic - G::BX2]) * c.inv_2dx;
+        lap += (U0[ic + G::BX2] - 2.0 * ph + U0[ic - G::BX2]);
+      }
+      const double upz = su[sp][0][ic], umz = su[sm][0][ic];
+      gph[DIM - 1] = (upz - umz) * c.inv_2dx;
+      gcs[DIM - 1] = (su[sp][1][ic] - su[sm][1][ic]) * c.inv_2dx;
+      gcl[DIM - 1] = (su[sp][2][ic] - su[sm][2][ic]) * c.inv_2dx;
+      lap += (upz - 2.0 * ph + umz);
+      lap *= c.inv_dx2;
+      double phit, mubar;
+      cell_stage<DIM>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
+      spt[pt][i] = phit;
+      smu[mu][i] = mubar;
+    }
+  };
+
+  // Flux through the z-face between planes gz and gz+1 of the own column.
+  auto zface = [&](int gz, double& Fs, double& Fl) {
+    if (gz < 0 || gz + 1 >= nz) {
+      Fs = 0.0;
+      Fl = 0.0;
+      return;
+    }
+    const int sa = (gz + 8) & 3, sb = (gz + 9) & 3;
+    const int pa = (gz + 8) & 1, pb = (gz + 9) & 1;
+    const int ma = (gz + 9) % 3, mb = (gz + 10) % 3;
+    const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
+    double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
+    const double pa_ = su[sa][0][ic], pb_ = su[sb][0][ic];
+    const double ca = su[sa][1][ic], cb = su[sb][1][ic];
+    const double la = su[sa][2][ic], lb = su[sb][2][ic];
+    const int k = DIM - 1;
+    gph[k] = (pb_ - pa_) * c.inv_dx;
+    gmu[k] = (smu[mb][i1] - smu[ma][i1]) * c.inv_dx;
+    gcs[k] = (cb - ca) * c.inv_dx;
+    gcl[k] = (lb - la) * c.inv_dx;
+    {  // x
+      gph[0] = 0.5 * ((su[sa][0][ic + 1] - su[sa][0][ic - 1]) * c.inv_2dx +
+                      (su[sb][0][ic + 1] - su[sb][0][ic - 1]) * c.inv_2dx);
+      gmu[0] = 0.5 * ((smu[ma][i1 + 1] - smu[ma][i1 - 1]) * c.inv_2dx +
+                      (smu[mb][i1 + 1] - smu[mb][i1 - 1]) * c.inv_2dx);
+      gcs[0] = 0.5 * ((su[sa][1][ic + 1] - su[sa][1][ic - 1]) * c.inv_2dx +
+                      (su[sb][1][ic + 1] - su[sb][1][ic - 1]) * c.inv_2dx);
+      gcl[0] = 0.5 * ((su[sa][2][ic + 1] - su[sa][2][ic - 1]) * c.inv_2dx +
+                      (su[sb][2][ic + 1] - su[sb][2][ic - 1]) * c.inv_2dx);
+    }
+    if (DIM == 3) {
+      const int d2 = G::BX2, d1 = G::BX1;
+      gph[1] = 0.5 * ((su[sa][0][ic + d2] - su[sa][0][ic - d2]) * c.inv_2dx +
+                      (su[sb][0][ic + d2] - su[sb][0][ic - d2]) * c.inv_2dx);
+      gmu[1] = 0.5 * ((smu[ma][i1 + d1] - smu[ma][i1 - d1]) * c.inv_2dx +
+                      (smu[mb][i1 + d1] - smu[mb][i1 - d1]) * c.inv_2dx);
+      gcs[1] = 0.5 * ((su[sa][1][ic + d2] - su[sa][1][ic - d2]) * c.inv_2dx +
+                      (su[sb][1][ic + d2] - su[sb][1][ic - d2]) * c.inv_2dx);
+      gcl[1] = 0.5 * ((su[sa][2][ic + d2] - su[sa][2][ic - d2]) * c.inv_2dx +
+                      (su[sb][2][ic + d2] - su[sb][2][ic - d2]) * c.inv_2dx);
+    }
+    const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
+    face_flux<DIM>(c, k, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
+                   Fl);
+  };
+
+  // x (and y) faces of plane gz into LDS.
+  auto xy_faces = [&](int gz) {
+    const int s0 = (gz + 8) & 3, sm = (gz + 7) & 3, sp = (gz + 9) & 3;
+    const int pt = (gz + 8) & 1;
+    const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
+    const int nxy = G::NFX + G::NFY;
+    for (int f = tid; f < nxy; f += G::NT) {
+      int k, la, lb_x, lb_y, lay;
+      if (f < G::NFX) {
+        k = 0;
+        const int fx = f % (TX + 1);
+        lay = f / (TX + 1);
+        la = fx - 1;
+        lb_x = fx;
+        lb_y = lay;
+        const int gface = x0 + fx;  // face between gx = gface-1 and gface
+        if ((!c.px && (gface == 0 || gface >= nx)) || gface > nx) {
+          sfx[0][f] = 0.0;
+          sfx[1][f] = 0.0;
+          continue;
+        }
+      } else {
+        k = 1;
+        const int g = f - G::NFX;
+        const int fy = g / TX;
+        la = g % TX;
+        lay = fy - 1;
+        lb_x = la;
+        lb_y = fy;
+        const int gface = y0 + fy;
+        if ((!c.py && (gface == 0 || gface >= ny)) || gface > ny) {
+          sfy[0][g] = 0.0;
+          sfy[1][g] = 0.0;
+          continue;
+        }
+      }
+      const int ia = G::i2(la, lay), ib = G::i2(lb_x, lb_y);
+      const int ja = G::i1(la, lay), jb = G::i1(lb_x, lb_y);
+      double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
+      const double pa = su[s0][0][ia], pb = su[s0][0][ib];
+      const double ca = su[s0][1][ia], cb = su[s0][1][ib];
+      const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
+      gph[k] = (pb - pa) * c.inv_dx;
+      gmu[k] = (smu[m0][jb] - smu[m0][ja]) * c.inv_dx;
+      gcs[k] = (cb - ca) * c.inv_dx;
+      gcl[k] = (lb_ - la_) * c.inv_dx;
+      // transverse in-plane axis (3D only): the other of x/y
+      if (DIM == 3) {
+        const int j = 1 - k;
+        const int d2 = (j == 0) ? 1 : G::BX2;
+        const int d1 = (j == 0) ? 1 : G::BX1;
+        gph[j] = 0.5 * ((su[s0][0][ia + d2] - su[s0][0][ia - d2]) * c.inv_2dx +
+                        (su[s0][0][ib + d2] - su[s0][0][ib - d2]) * c.inv_2dx);
+        gmu[j] = 0.5 * ((smu[m0][ja + d1] - smu[m0][ja - d1]) * c.inv_2dx +
+                        (smu[m0][jb + d1] - smu[m0][jb - d1]) * c.inv_2dx);
+        gcs[j] = 0.5 * ((su[s0][1][ia + d2] - su[s0][1][ia - d2]) * c.inv_2dx +
+                        (su[s0][1][ib + d2] - su[s0][1][ib - d2]) * c.inv_2dx);
+        gcl[j] = 0.5 * ((su[s0][2][ia + d2] - su[s0][2][ia - d2]) * c.inv_2dx +
+                        (su[s0][2][ib + d2] - su[s0][2][ib - d2]) * c.inv_2dx);
+      }
+      // transverse z
+      const int kz = DIM - 1;
+      gph[kz] = 0.5 * ((su[sp][0][ia] - su[sm][0][ia]) * c.inv_2dx + (su[sp][0][ib] - su[sm][0][ib]) * c.inv_2dx);
+      gmu[kz] = 0.5 * ((smu[mp][ja] - smu[mm][ja]) * c.inv_2dx + (smu[mp][jb] - smu[mm][jb]) * c.inv_2dx);
+      gcs[kz] = 0.5 * ((su[sp][1][ia] - su[sm][1][ia]) * c.inv_2dx + (su[sp][1][ib] - su[sm][1][ib]) * c.inv_2dx);
+      gcl[kz] = 0.5 * ((su[sp][2][ia] - su[sm][2][ia]) * c.inv_2dx + (su[sp][2][ib] - su[sm][2][ib]) * c.inv_2dx);
+      const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
+      double Fs, Fl;
+      face_flux<DIM>(c, k, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+      if (k == 0) {
+        sfx[0][f] = Fs;
+        sfx[1][f] = Fl;
+      } else {
+        sfy[0][f - G::NFX] = Fs;
+        sfy[1][f - G::NFX] = Fl;
+      }
+    }
+  };
+
+  // ---- prologue
+  for (int g = zb - 2; g <= zb + 1; ++g) load_plane(g);
+  __syncthreads();
+  cell_plane(zb - 1);
+  cell_plane(zb);
+  __syncthreads();
+  double FsD, FlD;  // flux through the face below the current plane
+  zface(zb - 1, FsD, FlD);
+
+  int errbits = 0;
+  for (int z = zb; z < ze; ++z) {
+    load_plane(z + 2);
+    __syncthreads();
+    cell_plane(z + 1);
+    __syncthreads();
+    xy_faces(z);
+    double FsU, FlU;
+    zface(z, FsU, FlU);
+    __syncthreads();
+    if (own_valid) {
+      const int s0 = (z + 8) & 3;
+      const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
+      const double ph = su[s0][0][ic], cs = su[s0][1][ic], cl = su[s0][2][ic];
+      const double pt = spt[(z + 8) & 1][i1];
+      double divs = sfx[0][oy * (TX + 1) + ox + 1] - sfx[0][oy * (TX + 1) + ox];
+      double divl = sfx[1][oy * (TX + 1) + ox + 1] - sfx[1][oy * (TX + 1) + ox];
+      if (DIM == 3) {
+        divs += sfy[0][(oy + 1) * TX + ox] - sfy[0][oy * TX + ox];
+        divl += sfy[1][(oy + 1) * TX + ox] - sfy[1][oy * TX + ox];
+      }
+      divs += FsU - FsD;
+      divl += FlU - FlD;
+      double p, q, dp;
+      interp(c, ph, p, q, dp);
+      const double src = -c.A * (cs - cl) * dp * pt;
+      const double ncs = cs + c.dt * (divs * c.inv_dx + src);
+      const double ncl = cl + c.dt * (divl * c.inv_dx + src);
+      const double nph = ph + c.dt * pt;
+      errbits |= check_bits(nph, ncs, ncl);
+      const long long col = (long long)gxo + (long long)nx * gyo;
+      if (!do_shift) {
+        const long long o = col + plane * z;
+        oph[o] = nph;
+        ocs[o] = ncs;
+        ocl[o] = ncl;
+      } else {
+        if (z >= 1) {
+          const long long o = col + plane * (z - 1);
+          oph[o] = nph;
+          ocs[o] = ncs;
+          ocl[o] = ncl;
+        }
+        if (z == nz - 1) {
+          const long long o = col + plane * z;
+          oph[o] = 0.0;
+          ocs[o] = c.ke;
+          ocl[o] = 1.0;
+        }
+      }
+    }
+    FsD = FsU;
+    FlD = FlU;
+  }
+  if (errbits) atomicOr(err, errbits);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent 1D kernel: one workgroup per run (single domain = one run),
+// runs taken longest first.  The whole run stays in registers for all steps:
+// thread t owns C = ceil(N / 1024) <= 8 consecutive cells; neighbour values are
+// exchanged through LDS (cells, then phi_t and mu_bar of the chunk edges), so
+// nothing is recomputed.  The window shift moves each chunk down by one cell
+// with one more exchange.  Optionally stores every state to a trajectory.
+// ---------------------------------------------------------------------------
+constexpr int R1_THREADS = 1024;
+constexpr int R1_CMAX = 8;
+
+struct RunTab {
+  const int* n;
+  const long long* off;
+  const double* V;
+  const double* dt;
+  const double* z0;
+  const int* order;  // launch order (longest first)
+};
+
+__global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double* __restrict__ gph,
+                                                      double* __restrict__ gcs, double* __restrict__ gcl,
+                                                      long long n0, long long nsteps, int do_shift,
+                                                      int* __restrict__ err, double* __restrict__ tph,
+                                                      double* __restrict__ tcs, double* __restrict__ tcl,
+                                                      long long tstride) {
+  __shared__ double xe[2][3][R1_THREADS];  // [first|last][phi, cs, cl][thread]
+  __shared__ double xd[2][2][R1_THREADS];  // [first|last][phi_t, mu_bar][thread]
+  const int r = rt.order[blockIdx.x];
+  const int N = rt.n[r];
+  const long long off = rt.off[r];
+  const double V = rt.V[r], dt = rt.dt[r], z0 = rt.z0[r];
+  const int C = (N + R1_THREADS - 1) / R1_THREADS;
+  const int t = threadIdx.x;
+  const int i0 = t * C;
+  const int cnt = max(0, min(C, N - i0));
+  const bool at_lo = (i0 == 0);
+  const bool at_hi = (cnt > 0) && (i0 + cnt == N);
+  const bool has_right = (cnt > 0) && !at_hi;  // thread t+1 owns cell i0 + cnt
+
+  double P[R1_CMAX], S[R1_CMAX], L[R1_CMAX];
+  // value of register array a at runtime position idx (static selects, no scratch)
+  auto pick = [](const double (&a)[R1_CMAX], int idx) {
+    double v = a[0];
+#pragma unroll
+    for (int k = 1; k < R1_CMAX; ++k) v = (k == idx) ? a[k] : v;
+    return v;
+  };
+#pragma unroll
+  for (int k = 0; k < R1_CMAX; ++k) {
+    if (k < cnt) {
+      P[k] = gph[off + i0 + k];
+      S[k] = gcs[off + i0 + k];
+      L[k] = gcl[off + i0 + k];
+    } else {
+      P[k] = 0.0;
+      S[k] = 1.0;
+      L[k] = 1.0;
+    }
+  }
+  int errbits = 0;
+  for (long long st = 0; st <= nsteps; ++st) {
+    const long long n = n0 + st;
+    if (tph) {
+#pragma unroll
+      for (int k = 0; k < R1_CMAX; ++k)
+        if (k < cnt) {
+          const long long o = st * tstride + off + i0 + k;
+          tph[o] = P[k];
+          tcs[o] = S[k];
+          tcl[o] = L[k];
+        }
+    }
+    if (st == nsteps) break;
+    const double tn = (double)n * dt;
+    const double sn = floor(V * tn / c.dx);
+    const bool shift = do_shift && (floor(V * ((double)(n + 1) * dt) / c.dx) > sn);
+    // exchange 1: chunk edge cells
+    if (cnt > 0) {
+      xe[0][0][t] = P[0];
+      xe[0][1][t] = S[0];
+      xe[0][2][t] = L[0];
+      xe[1][0][t] = pick(P, cnt - 1);
+      xe[1][1][t] = pick(S, cnt - 1);
+      xe[1][2][t] = pick(L, cnt - 1);
+    }
+    __syncthreads();
+    double lP, lS, lL, rP, rS, rL;  // left of first cell, right of last cell (mirror at the ends)
+    if (at_lo) {
+      lP = P[0];
+      lS = S[0];
+      lL = L[0];
+    } else {
+      lP = xe[1][0][t - 1];
+      lS = xe[1][1][t - 1];
+      lL = xe[1][2][t - 1];
+    }
+    if (has_right) {
+      rP = xe[0][0][t + 1];
+      rS = xe[0][1][t + 1];
+      rL = xe[0][2][t + 1];
+    } else {
+      rP = pick(P, cnt - 1);
+      rS = pick(S, cnt - 1);
+      rL = pick(L, cnt - 1);
+    }
+    // cell stage
+    double PT[R1_CMAX], MU[R1_CMAX];
+#pragma unroll
+    for (int k = 0; k < R1_CMAX; ++k) {
+      PT[k] = 0.0;
+      MU[k] = 0.0;
+      if (k < cnt) {
+        const double pm = (k == 0) ? lP : P[k - 1], pp = (k == cnt - 1) ? rP : P[(k + 1 < R1_CMAX) ? k + 1 : k];
+        const double sm = (k == 0) ? lS : S[k - 1], sp = (k == cnt - 1) ? rS : S[(k + 1 < R1_CMAX) ? k + 1 : k];
+        const double lm = (k == 0) ? lL : L[k - 1], lp = (k == cnt - 1) ? rL : L[(k + 1 < R1_CMAX) ? k + 1 : k];
+        double gph1[1] = {(pp - pm) * c.inv_2dx};
+        double gcs1[1] = {(sp - sm) * c.inv_2dx};
+        double gcl1[1] = {(lp - lm) * c.inv_2dx};
+        const double lap = (pp - 2.0 * P[k] + pm) * c.inv_dx2;
+        const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
+        const double cleq = cleq_at(c, zlab, tn, V, z0);
+        cell_stage<1>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
+      }
+    }
+    // exchange 2: phi_t and mu_bar of the chunk edges
+    if (cnt > 0) {
+      xd[0][0][t] = PT[0];
+      xd[0][1][t] = MU[0];
+      xd[1][0][t] = pick(PT, cnt - 1);
+      xd[1][1][t] = pick(MU, cnt - 1);
+    }
+    __syncthreads();
+    const double lPT = at_lo ? 0.0 : xd[1][0][t - 1];
+    const double lMU = at_lo ? 0.0 : xd[1][1][t - 1];
+    const double rPT = has_right ? xd[0][0][t + 1] : 0.0;
+    const double rMU = has_right ? xd[0][1][t + 1] : 0.0;
+    // faces j = 0..cnt: face j lies between local cells j-1 and j
+    double FS[R1_CMAX + 1], FL[R1_CMAX + 1];
+#pragma unroll
+    for (int j = 0; j <= R1_CMAX; ++j) {
+      FS[j] = 0.0;
+      FL[j] = 0.0;
+      if (cnt > 0 && j <= cnt) {
+        const bool boundary = (j == 0 && at_lo) || (j == cnt && at_hi);
+        if (!boundary) {
+          const double pa = (j == 0) ? lP : P[(j > 0 ? j : 1) - 1];
+          const double sa = (j == 0) ? lS : S[(j > 0 ? j : 1) - 1];
+          const double la = (j == 0) ? lL : L[(j > 0 ? j : 1) - 1];
+          const double ta = (j == 0) ? lPT : PT[(j > 0 ? j : 1) - 1];
+          const double ma = (j == 0) ? lMU : MU[(j > 0 ? j : 1) - 1];
+          const double pb = (j == cnt) ? rP : P[(j < R1_CMAX) ? j : R1_CMAX - 1];
+          const double sb = (j == cnt) ? rS : S[(j < R1_CMAX) ? j : R1_CMAX - 1];
+          const double lb = (j == cnt) ? rL : L[(j < R1_CMAX) ? j : R1_CMAX - 1];
+          const double tb = (j == cnt) ? rPT : PT[(j < R1_CMAX) ? j : R1_CMAX - 1];
+          const double mb = (j == cnt) ? rMU : MU[(j < R1_CMAX) ? j : R1_CMAX - 1];
+          double g0[1] = {(pb - pa) * c.inv_dx};
+          double g1[1] = {(mb - ma) * c.inv_dx};
+          double g2[1] = {(sb - sa) * c.inv_dx};
+          double g3[1] = {(lb - la) * c.inv_dx};
+          face_flux<1>(c, 0, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3,
+                       FS[j], FL[j]);
+        }
+      }
+    }
+    // update
+#pragma unroll
+    for (int k = 0; k < R1_CMAX; ++k) {
+      if (k < cnt) {
+        double p, q, dp;
+        interp(c, P[k], p, q, dp);
+        const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
+        const double ns = S[k] + dt * ((FS[k + 1] - FS[k]) * c.inv_dx + src);
+        const double nl = L[k] + dt * ((FL[k + 1] - FL[k]) * c.inv_dx + src);
+        P[k] = P[k] + dt * PT[k];
+        S[k] = ns;
+        L[k] = nl;
+        errbits |= check_bits(P[k], S[k], L[k]);
+      }
+    }
+    if (shift) {  // uniform across the workgroup
+      // every thread's first cell moves to its left neighbour's last slot
+      __syncthreads();  // all reads of xe from exchange 1 are done (barrier 2 passed too)
+      if (cnt > 0) {
+        xe[0][0][t] = P[0];
+        xe[0][1][t] = S[0];
+        xe[0][2][t] = L[0];
+      }
+      __syncthreads();
+      double nP, nS, nL;
+      if (has_right) {
+        nP = xe[0][0][t + 1];
+        nS = xe[0][1][t + 1];
+        nL = xe[0][2][t + 1];
+      } else {
+        nP = 0.0;
+        nS = c.ke;
+        nL = 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < R1_CMAX; ++k) {
+        if (k < cnt) {
+          const bool last = (k == cnt - 1);
+          P[k] = last ? nP : P[(k + 1 < R1_CMAX) ? k + 1 : k];
+          S[k] = last ? nS : S[(k + 1 < R1_CMAX) ? k + 1 : k];
+          L[k] = last ? nL : L[(k + 1 < R1_CMAX) ? k + 1 : k];
+        }
+      }
+    }
+    __syncthreads();  // exchange buffers are rewritten by the next step
+  }
+#pragma unroll
+  for (int k = 0; k < R1_CMAX; ++k)
+    if (k < cnt) {
+      gph[off + i0 + k] = P[k];
+      gcs[off + i0 + k] = S[k];
+      gcl[off + i0 + k] = L[k];
+    }
+  if (errbits) atomicOr(err, errbits);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  Cells of each "run" (a batched 1D run, or the
+// single domain as run 0) are cut into chunks of RED_CHUNK cells; one
+// workgroup per chunk writes partials, then one workgroup per run reduces its
+// chunks in index order.  Fixed trees, so results do not depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+constexpr int RED_CHUNK = 4096;
+
+struct RedTab {
+  const int* chunk_run;        // run of chunk
+  const long long* chunk_beg;  // first cell (relative to the run) of chunk
+  const int* run_chunk0;       // first chunk of run (nrun + 1 entries)
+};
+
+struct Partial {
+  double energy, solute, cmax;
+  long long arg;
+};
+
+__device__ __forceinline__ void better(double& v, long long& a, double v2, long long a2) {
+  if (v2 > v || (v2 == v && a2 < a)) {
+    v = v2;
+    a = a2;
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_chunks(Const c, RunTab rt, RedTab red,
+                                                               const double* __restrict__ ph,
+                                                               const double* __restrict__ cs,
+                                                               const double* __restrict__ cl, long long n,
+                                                               int batched, Partial* __restrict__ out) {
+  __shared__ double se[RED_THREADS], ss[RED_THREADS], sm[RED_THREADS];
+  __shared__ long long sa[RED_THREADS];
+  const int ch = blockIdx.x;
+  const int r = red.chunk_run[ch];
+  const long long beg = red.chunk_beg[ch];
+  const long long N = batched ? (long long)rt.n[r] : c.ncell;
+  const long long off = batched ? rt.off[r] : 0;
+  const double V = batched ? rt.V[r] : c.V;
+  const double dt = batched ? rt.dt[r] : c.dt;
+  const double z0 = batched ? rt.z0[r] : c.z0;
+  const double tn = (double)n * dt;
+  const double sn = floor(V * tn / c.dx);
+  const long long end = min(beg + (long long)RED_CHUNK, N);
+  const int nx = batched ? 1 : c.nx, ny = batched ? 1 : c.ny, nz = batched ? (int)N : c.nz;
+  const long long plane = (long long)nx * ny;
+  double e = 0.0, s = 0.0, mx = -INFINITY;
+  long long am = -1;
+  for (long long i = beg + threadIdx.x; i < end; i += RED_THREADS) {
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int z = (int)(i / plane);
+    const double f = ph[off + i], a = cs[off + i], b = cl[off + i];
+    double p, q;
+    interp_pq(c, f, p, q);
+    const double zlab = ((double)z + sn + 0.5) * c.dx;
+    const double cleq = cleq_at(c, zlab, tn, V, z0);
+    const double fs = a * log(a) - a - a * c.log_ke + (c.ke - 1.0) * cleq;
+    const double fl = b * log(b) - b;
+    const double w = f * (1.0 - f);
+    double en = w * w + c.lambda * (p * fs + q * fl);
+    // gradient energy on the faces above the cell (each face once)
+    double gsum = 0.0;
+    if (batched || c.dim == 1) {
+      if (z + 1 < nz) {
+        const double d = (ph[off + i + plane] - f) * c.inv_dx;
+        gsum += d * d;
+      }
+    } else {
+      if (c.px || x + 1 < nx) {
+        const long long j = (long long)((x + 1) % nx) + (long long)nx * y + plane * z;
+        const double d = (ph[j] - f) * c.inv_dx;
+        gsum += d * d;
+      }
+      if (c.dim == 3 && (c.py || y + 1 < ny)) {
+        const long long j = (long long)x + (long long)nx * ((y + 1) % ny) + plane * z;
+        const double d = (ph[j] - f) * c.inv_dx;
+        gsum += d * d;
+      }
+      if (z + 1 < nz) {
+        const double d = (ph[i + plane] - f) * c.inv_dx;
+        gsum += d * d;
+      }
+    }
+    en += 0.5 * c.W2 * gsum;
+    e += en;
+    const double cc = p * a + q * b;
+    s += cc;
+    better(mx, am, cc, i);
+  }
+  se[threadIdx.x] = e;
+  ss[threadIdx.x] = s;
+  sm[threadIdx.x] = mx;
+  sa[threadIdx.x] = am;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      se[threadIdx.x] += se[threadIdx.x + w];
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      double v = sm[threadIdx.x];
+      long long a = sa[threadIdx.x];
+      better(v, a, sm[threadIdx.x + w], sa[threadIdx.x + w]);
+      sm[threadIdx.x] = v;
+      sa[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[ch].energy = se[0];
+    out[ch].solute = ss[0];
+    out[ch].cmax = sm[0];
+    out[ch].arg = sa[0];
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_runs(Const c, RedTab red, const Partial* __restrict__ in,
+                                                             Partial* __restrict__ out) {
+  __shared__ double se[RED_THREADS], ss[RED_THREADS], sm[RED_THREADS];
+  __shared__ long long sa[RED_THREADS];
+  const int r = blockIdx.x;
+  const int c0 = red.run_chunk0[r], c1 = red.run_chunk0[r + 1];
+  double e = 0.0, s = 0.0, mx = -INFINITY;
+  long long am = -1;
+  for (int k = c0 + threadIdx.x; k < c1; k += RED_THREADS) {
+    e += in[k].energy;
+    s += in[k].solute;
+    better(mx, am, in[k].cmax, in[k].arg);
+  }
+  se[threadIdx.x] = e;
+  ss[threadIdx.x] = s;
+  sm[threadIdx.x] = mx;
+  sa[threadIdx.x] = am;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      se[threadIdx.x] += se[threadIdx.x + w];
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      double v = sm[threadIdx.x];
+      long long a = sa[threadIdx.x];
+      better(v, a, sm[threadIdx.x + w], sa[threadIdx.x + w]);
+      sm[threadIdx.x] = v;
+      sa[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double vol = 1.0;
+    for (int k = 0; k < c.dim; ++k) vol *= c.dx;
+    out[r].energy = se[0] * vol;
+    out[r].solute = ss[0] * vol;
+    out[r].cmax = sm[0];
+    out[r].arg = sa[0];
+  }
+}
+
+// Seed of the k_v loss: lam = sum_r dL/dk_r dk_r/du at each run's argmax cell.
+__global__ void k_kv_seed(Const c, RunTab rt, int batched, const Partial* __restrict__ red,
+                          const double* __restrict__ dLdk, int nrun, double* __restrict__ lph,
+                          double* __restrict__ lcs, double* __restrict__ lcl, const double* __restrict__ ph,
+                          const double* __restrict__ cs, const double* __restrict__ cl) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrun) return;
+  const long long off = batched ? rt.off[r] : 0;
+  const long long j = off + red[r].arg;
+  if (red[r].arg < 0) return;
+  const double cm = red[r].cmax;
+  const double g = dLdk[r] / (cm * cm);
+  double p, q, dp;
+  interp(c, ph[j], p, q, dp);
+  lph[j] = -g * dp * (cs[j] - cl[j]);
+  lcs[j] = -g * p;
+  lcl[j] = -g * q;
+}
+
+__global__ void k_fill(double* __restrict__ a, double v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+}  // namespace pfk

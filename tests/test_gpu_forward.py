@@ -1,0 +1,178 @@
+"""GPU parity of the forward step (through the C ABI) against the CPU oracle.
+
+Bar: max relative field error max|x - ref| / max|ref| <= 1e-10 per field
+after the whole run, element by element, on the same seeded inputs.
+Cases span several tiles with ragged tails, the window shift, mirror and
+periodic transverse axes, batched runs of uneven length (C = 1..8 cells per
+thread), and at the full workload sizes one step on sampled grids.
+"""
+import numpy as np
+import pytest
+
+from paper_2303_09671_amd import inputs as I
+from tests.helpers import TOL, assert_parity, oracle_batch, oracle_params, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def _run_gpu(torch, p, fields, nsteps, runs=None, offsets=None, expect=0):
+    from paper_2303_09671_amd import pf
+    t = [_dev(torch, a) for a in fields]
+    h = pf.pf_create(p, *t, runs=runs, offsets=offsets)
+    pf.pf_step(h, nsteps)
+    torch.cuda.synchronize()
+    assert pf.pf_check(h) == expect
+    out = [x.cpu().numpy() for x in t]
+    return h, t, out
+
+
+def test_1d_full_run(torch_dev, oracle):
+    """The 1D workload as configured: N = 1024, 20000 steps, V = 0.1."""
+    p, steps = I.config_1d()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    print("case: 1D N=1024 steps=20000", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert_parity(g, ref[:3], what="1D full")
+    from paper_2303_09671_amd import pf
+    tot, cm, am = pf.pf_solute(h)
+    rt, rcm, ram = oracle.solute(oracle_params(oracle, p), *ref[:3])
+    assert abs(cm[0] - rcm) <= TOL * rcm and abs(tot[0] - rt) <= 1e-12 * abs(rt)
+    assert am[0] == ram or abs(g[0][am[0]] - ref[0][am[0]]) < 1e-9  # unique max, or a tie to rounding
+    E = pf.pf_energy(h)[0]
+    assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
+
+
+@pytest.mark.parametrize("Ns", [(37, 600, 1024, 1025, 3001), (8192, 512, 4096, 77)])
+def test_1d_batch(torch_dev, oracle, Ns):
+    """Uneven runs (1..8 cells per thread, ragged chunks).  The 37-cell run is
+    too short for its front: the oracle goes non-finite, and so must the GPU
+    run, with the error word raised, while the other runs stay exact."""
+    runs = []
+    for i, N in enumerate(Ns):
+        V = [0.02, 0.1, 0.3, 0.05, 0.2][i % 5]
+        runs.append(dict(N=N, V=V, dt=I.run_dt(V), z0=(N // 4) * I.DX))
+    base = I.base_params(dim=1)
+    phi, cs, cl, offs = I.batch_fields(runs)
+    steps = 1500
+    print(f"case: batch {Ns} steps={steps}", flush=True)
+    refs = oracle_batch(oracle, base, runs, steps)
+    finite = [all(np.isfinite(a).all() for a in ref) for ref in refs]
+    from paper_2303_09671_amd import pf
+    h, t, g = _run_gpu(torch_dev, base, (phi, cs, cl), steps, runs=runs, offsets=offs,
+                       expect=pf.PF_OK if all(finite) else pf.PF_ENONFINITE)
+    for r, o, ref, fin in zip(runs, offs, refs, finite):
+        gr = [a[o:o + r["N"]] for a in g]
+        if fin:
+            assert_parity(gr, ref, what=f"run N={r['N']}")
+        else:
+            assert not all(np.isfinite(a).all() for a in gr), f"run N={r['N']} should be non-finite"
+    tot, cm, am = pf.pf_solute(h)
+    E = pf.pf_energy(h)
+    for i, (r, ref, fin) in enumerate(zip(runs, refs, finite)):
+        if not fin:
+            continue
+        po = oracle_params(oracle, dict(base, n=(r["N"], 1, 1), V=r["V"], dt=r["dt"], z0=r["z0"]))
+        rt, rcm, _ = oracle.solute(po, *ref)
+        assert abs(cm[i] - rcm) <= TOL * rcm
+        s = int(np.floor(r["V"] * (steps * r["dt"]) / base["dx"]))
+        assert abs(E[i] - oracle.energy(po, *ref, n=steps, shift=s)) <= 1e-10 * abs(E[i])
+
+
+@pytest.mark.parametrize("periodic", [1, 0])
+def test_2d_ragged_with_shift(torch_dev, oracle, periodic):
+    p, _, pert = I.config_2d(nx=150, nz=75)
+    p = dict(p, periodic=(periodic, 0, 0), V=0.5)  # a window shift every 50 steps
+    f = [a.ravel() for a in I.planar_front(2, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+    steps = 260
+    print(f"case: 2D 150x75 periodic={periodic} steps={steps}", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert ref[3] == 5
+    assert_parity(g, ref[:3], what="2D ragged")
+    from paper_2303_09671_amd import pf
+    tot, cm, am = pf.pf_solute(h)
+    rt, rcm, _ = oracle.solute(oracle_params(oracle, p), *ref[:3])
+    assert abs(cm[0] - rcm) <= TOL * rcm and abs(tot[0] - rt) <= 1e-12 * abs(rt)
+    E = pf.pf_energy(h)[0]
+    assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
+
+
+@pytest.mark.parametrize("periodic", [(1, 1), (0, 1)])
+def test_3d_ragged_with_shift(torch_dev, oracle, periodic):
+    p, _, pert = I.config_3d(n=8)
+    p = dict(p, n=(40, 12, 45), periodic=(periodic[0], periodic[1], 0), V=0.6, z0=14 * 0.8)
+    f = [a.ravel() for a in I.planar_front(3, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+    steps = 90  # two shifts
+    print(f"case: 3D 40x12x45 periodic={periodic} steps={steps}", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert ref[3] == 2
+    assert_parity(g, ref[:3], what="3D ragged")
+    from paper_2303_09671_amd import pf
+    E = pf.pf_energy(h)[0]
+    assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+def test_full_size_one_step(torch_dev, oracle, which):
+    """Workload sizes as configured (2D 1024^2, 3D 256^3), same launch
+    configuration as the benchmark: advance 40 steps on the GPU, then compare
+    one more GPU step with one oracle step from the GPU's state, on every cell."""
+    if which == "2d":
+        p, _, pert = I.config_2d()
+    else:
+        p, _, pert = I.config_3d()
+    f = [a.ravel() for a in I.planar_front(p["dim"], p["n"], p["dx"], p["z0"], p["ke"], amp=pert["amp"],
+                                           seed=pert["seed"])]
+    print(f"case: full-size {which} one step", flush=True)
+    from paper_2303_09671_amd import pf
+    h, t, g40 = _run_gpu(torch_dev, p, f, 40)
+    pf.pf_step(h, 1)
+    torch_dev.cuda.synchronize()
+    g41 = [x.cpu().numpy() for x in t]
+    s40 = int(np.floor(p["V"] * (40 * p["dt"]) / p["dx"]))
+    ref = oracle.step(oracle_params(oracle, p), *g40, 1, n0=40, shift=s40)
+    assert_parity(g41, ref[:3], what=f"full-size {which}")
+
+
+def test_error_paths(torch_dev):
+    from paper_2303_09671_amd import pf
+    p, _ = I.config_1d(N=64)
+    p = dict(p, z0=16 * I.DX)
+    f = list(I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"]))
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(dict(p, dt=1.0), *[_dev(torch_dev, a) for a in f])
+    assert e.value.code == pf.PF_EUNSTABLE_DT
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(dict(p, b=1e-3, ap=11.0), *[_dev(torch_dev, a) for a in f])
+    assert e.value.code == pf.PF_EINVAL
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(dict(p, ke=1.5), *[_dev(torch_dev, a) for a in f])
+    assert e.value.code == pf.PF_EINVAL
+    # a NaN planted by the host is reported
+    bad = [a.copy() for a in f]
+    bad[1][40] = np.nan
+    h = pf.pf_create(p, *[_dev(torch_dev, a) for a in bad])
+    pf.pf_step(h, 3)
+    assert pf.pf_check(h) == pf.PF_ENONFINITE
+    assert pf.pf_check(h) == pf.PF_OK  # cleared
+    # a negative concentration is reported; check_every makes pf_step report it
+    bad = [a.copy() for a in f]
+    bad[2][50] = -0.5
+    h = pf.pf_create(dict(p, check_every=2), *[_dev(torch_dev, a) for a in bad])
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_step(h, 4)
+    assert e.value.code in (pf.PF_ENEGCONC, pf.PF_ENONFINITE)
