@@ -21,10 +21,20 @@ struct Const {
   int quintic, pad_;
   long long ncell;
   // model
-  double dx, inv_dx, inv_2dx, inv_dx2, dt;
+  double dx, inv_dx, inv_2dx, inv_4dx, inv_dx2, dt;
   double W, W2, alpha, lambda, lambda0, Mphi;
   double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad;
 };
+
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each step squares the relative error); x is positive and normal here.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 
 // Interpolation p(phi) = h + a_p (phi - 1/2) phi^2 (1-phi)^2 (Eq. interpolation2),
 // its complement q = 1 - p evaluated as p(1 - phi) (antisymmetry of p; avoids the
@@ -82,6 +92,13 @@ __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs
 // Cell stage: phi_t (Eq. phasefield_nonvar divided by H) and mu_bar.
 //   g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
 //   compact Laplacian of phi.
+// With Mbar = M_s(1-p) + b M_l p, G = |grad phi|^2 and the drag numerator
+// Dn = M_s(1-p)(1 - A(1-p)) + A b M_l p^2 (drag D = Dn / Mbar), the rate
+//   phi_t = [W^2 lap - f' - lambda (dG_c - D dc dmu) p' + X] / tau,
+//   X   = lambda (1-A) dc p(1-p) (Ds grad c_s - b grad c_l).grad phi / (Mbar G),
+//   tau = alpha + lambda (1-A)^2 dc^2 b p(1-p) / (Mbar G (b p + 1 - p)),
+// is evaluated with numerator and prefactor multiplied by Q = Mbar G (b p + 1 - p)
+// (by Mbar alone below the gate, where X = 0 and tau = alpha): one division.
 template <int DIM>
 __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
                                            const double* gph, const double* gcs, const double* gcl,
@@ -95,33 +112,39 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
   const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;  // Eq. dil5.2 with Eq. ds3
   const double ms = c.Ds * cs * q;                          // M_s (1 - p)
   const double ml = c.b * cl * p;                           // b M_l p
-  const double iM = 1.0 / (ms + ml);                        // 1 / Mbar
-  const double drag = (ms * (1.0 - c.A * q) + c.A * ml * p) * iM;
-  const double dG = dGc - drag * dc * dmu;
+  const double Mb = ms + ml;
+  const double Dn = ms * (1.0 - c.A * q) + c.A * ml * p;
   double G = 0.0, dot = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     G += gph[k] * gph[k];
     dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
   }
-  const double gam = (G > c.eps_grad) ? 1.0 / G : 0.0;
+  const bool on = G > c.eps_grad;
+  const double bq = c.b * p + q;
+  const double Gp = on ? G * bq : 1.0;
+  const double Q = Mb * Gp;
   const double pq = p * q;
   const double lAdc = c.lambda * c.onemA * dc;
-  const double tau = c.alpha + lAdc * c.onemA * dc * c.b * pq * gam * iM / (c.b * p + q);
-  const double X = lAdc * pq * iM * dot * gam;
   const double fdw = 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
-  phit = (c.W2 * lap - fdw - c.lambda * dG * dp + X) / tau;
+  const double base = c.W2 * lap - fdw - c.lambda * dGc * dp;
+  const double num = base * Q + c.lambda * Dn * dc * dmu * dp * Gp + (on ? lAdc * pq * dot * bq : 0.0);
+  const double den = c.alpha * Q + (on ? lAdc * c.onemA * dc * c.b * pq : 0.0);
+  phit = num * frcp(den);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
-// through a face normal to axis k.  phf, csf, clf, ptf are the face means;
-// g*[j] the face gradient (compact along k, mean of central differences
-// across k) of phi, mu_bar, c_s, c_l.
-template <int DIM>
-__device__ __forceinline__ void face_flux(const Const& c, int k, double phf, double csf, double clf,
-                                          double ptf, const double* gph, const double* gmu,
-                                          const double* gcs, const double* gcl, double& Fs,
-                                          double& Fl) {
+// through a face normal to axis K.  phf, csf, clf, ptf are the face means;
+// g*[j] the face gradient (compact along K, mean of central differences
+// across K) of phi, mu_bar, c_s, c_l.  With R = (grad phi)_K / (Mbar G):
+//   q_n (n n^T grad mu_bar)_K = M_s M_l (b p + 1 - p) (grad phi . grad mu_bar) R,
+//   ((1 - n n^T) grad c)_K    = (grad c)_K - (grad phi . grad c) Mbar R,
+//   anti-trapping_s / _l      = +/- (1-A)(c_s - c_l) phi_t R M_s(1-p) / b M_l p;
+// below the gate R = 0 and only the tangential parts remain.
+template <int DIM, int K>
+__device__ __forceinline__ void face_flux(const Const& c, double phf, double csf, double clf, double ptf,
+                                          const double* gph, const double* gmu, const double* gcs,
+                                          const double* gcl, double& Fs, double& Fl) {
   double p, q;
   interp_pq(c, phf, p, q);
   double G = 0.0, dmu = 0.0, dcs = 0.0, dcl = 0.0;
@@ -132,17 +155,15 @@ __device__ __forceinline__ void face_flux(const Const& c, int k, double phf, dou
     dcs += gph[j] * gcs[j];
     dcl += gph[j] * gcl[j];
   }
-  const double gam = (G > c.eps_grad) ? 1.0 / G : 0.0;
-  const double gk = gph[k] * gam;
   const double Ms = c.Ds * csf;
   const double Ml = clf;
   const double ms = Ms * q, ml = c.b * Ml * p;
-  const double iM = 1.0 / (ms + ml);
-  const double qn = Ms * Ml * (c.b * p + q) * iM;
-  const double nrm = qn * dmu * gk;                       // q_n (n n^T grad mu_bar)_k
-  const double at = c.onemA * (csf - clf) * gk * ptf * iM;  // anti-trapping / Mbar
-  Fs = nrm + c.Ds * (gcs[k] - dcs * gk) + at * ms;
-  Fl = nrm + (gcl[k] - dcl * gk) - at * ml;
+  const double Mb = ms + ml;
+  const double R = (G > c.eps_grad) ? gph[K] * frcp(Mb * G) : 0.0;
+  const double nrm = Ms * Ml * (c.b * p + q) * dmu * R;
+  const double at = c.onemA * (csf - clf) * ptf * R;
+  Fs = nrm + c.Ds * (gcs[K] - dcs * Mb * R) + at * ms;
+  Fl = nrm + (gcl[K] - dcl * Mb * R) - at * ml;
 }
 
 // Error word bits.

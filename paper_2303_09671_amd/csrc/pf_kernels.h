@@ -3,6 +3,8 @@
 // reductions (energy, solute, c_max) and the k_v adjoint seed.
 #pragma once
 
+#include <type_traits>
+
 #include "pf_device.h"
 
 namespace pfk {
@@ -12,6 +14,7 @@ namespace pfk {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int mirror_idx(int g, int n) {
   // reflect about the outer faces: -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2
+  if (g >= 0 && g < n) return g;
   while (g < 0 || g >= n) {
     if (g < 0) g = -g - 1;
     if (g >= n) g = 2 * n - g - 1;
@@ -19,7 +22,10 @@ __device__ __forceinline__ int mirror_idx(int g, int n) {
   return g;
 }
 __device__ __forceinline__ int map_axis(int g, int n, int periodic) {
+  if (g >= 0 && g < n) return g;
   if (periodic) {
+    if (g < 0 && g + n >= 0) return g + n;
+    if (g >= n && g - n < n) return g - n;
     g %= n;
     return g < 0 ? g + n : g;
   }
@@ -153,107 +159,75 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     gcs[k] = (cb - ca) * c.inv_dx;
     gcl[k] = (lb - la) * c.inv_dx;
     {  // x
-      gph[0] = 0.5 * ((su[sa][0][ic + 1] - su[sa][0][ic - 1]) * c.inv_2dx +
-                      (su[sb][0][ic + 1] - su[sb][0][ic - 1]) * c.inv_2dx);
-      gmu[0] = 0.5 * ((smu[ma][i1 + 1] - smu[ma][i1 - 1]) * c.inv_2dx +
-                      (smu[mb][i1 + 1] - smu[mb][i1 - 1]) * c.inv_2dx);
-      gcs[0] = 0.5 * ((su[sa][1][ic + 1] - su[sa][1][ic - 1]) * c.inv_2dx +
-                      (su[sb][1][ic + 1] - su[sb][1][ic - 1]) * c.inv_2dx);
-      gcl[0] = 0.5 * ((su[sa][2][ic + 1] - su[sa][2][ic - 1]) * c.inv_2dx +
-                      (su[sb][2][ic + 1] - su[sb][2][ic - 1]) * c.inv_2dx);
+      gph[0] = ((su[sa][0][ic + 1] - su[sa][0][ic - 1]) + (su[sb][0][ic + 1] - su[sb][0][ic - 1])) * c.inv_4dx;
+      gmu[0] = ((smu[ma][i1 + 1] - smu[ma][i1 - 1]) + (smu[mb][i1 + 1] - smu[mb][i1 - 1])) * c.inv_4dx;
+      gcs[0] = ((su[sa][1][ic + 1] - su[sa][1][ic - 1]) + (su[sb][1][ic + 1] - su[sb][1][ic - 1])) * c.inv_4dx;
+      gcl[0] = ((su[sa][2][ic + 1] - su[sa][2][ic - 1]) + (su[sb][2][ic + 1] - su[sb][2][ic - 1])) * c.inv_4dx;
     }
     if (DIM == 3) {
       const int d2 = G::BX2, d1 = G::BX1;
-      gph[1] = 0.5 * ((su[sa][0][ic + d2] - su[sa][0][ic - d2]) * c.inv_2dx +
-                      (su[sb][0][ic + d2] - su[sb][0][ic - d2]) * c.inv_2dx);
-      gmu[1] = 0.5 * ((smu[ma][i1 + d1] - smu[ma][i1 - d1]) * c.inv_2dx +
-                      (smu[mb][i1 + d1] - smu[mb][i1 - d1]) * c.inv_2dx);
-      gcs[1] = 0.5 * ((su[sa][1][ic + d2] - su[sa][1][ic - d2]) * c.inv_2dx +
-                      (su[sb][1][ic + d2] - su[sb][1][ic - d2]) * c.inv_2dx);
-      gcl[1] = 0.5 * ((su[sa][2][ic + d2] - su[sa][2][ic - d2]) * c.inv_2dx +
-                      (su[sb][2][ic + d2] - su[sb][2][ic - d2]) * c.inv_2dx);
+      gph[1] = ((su[sa][0][ic + d2] - su[sa][0][ic - d2]) + (su[sb][0][ic + d2] - su[sb][0][ic - d2])) * c.inv_4dx;
+      gmu[1] = ((smu[ma][i1 + d1] - smu[ma][i1 - d1]) + (smu[mb][i1 + d1] - smu[mb][i1 - d1])) * c.inv_4dx;
+      gcs[1] = ((su[sa][1][ic + d2] - su[sa][1][ic - d2]) + (su[sb][1][ic + d2] - su[sb][1][ic - d2])) * c.inv_4dx;
+      gcl[1] = ((su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2])) * c.inv_4dx;
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
-    face_flux<DIM>(c, k, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
+    face_flux<DIM, DIM - 1>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
                    Fl);
   };
 
-  // x (and y) faces of plane gz into LDS.
-  auto xy_faces = [&](int gz) {
+  // Faces normal to in-plane axis K (0 = x, 1 = y) of plane gz into LDS.
+  auto inplane_faces = [&](auto axis, int gz) {
+    constexpr int K = decltype(axis)::value;
+    constexpr int NF = (K == 0) ? G::NFX : G::NFY;
+    constexpr int RW = (K == 0) ? TX + 1 : TX;  // faces per row
     const int s0 = (gz + 8) & 3, sm = (gz + 7) & 3, sp = (gz + 9) & 3;
     const int pt = (gz + 8) & 1;
     const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
-    const int nxy = G::NFX + G::NFY;
-    for (int f = tid; f < nxy; f += G::NT) {
-      int k, la, lb_x, lb_y, lay;
-      if (f < G::NFX) {
-        k = 0;
-        const int fx = f % (TX + 1);
-        lay = f / (TX + 1);
-        la = fx - 1;
-        lb_x = fx;
-        lb_y = lay;
-        const int gface = x0 + fx;  // face between gx = gface-1 and gface
-        if ((!c.px && (gface == 0 || gface >= nx)) || gface > nx) {
-          sfx[0][f] = 0.0;
-          sfx[1][f] = 0.0;
-          continue;
-        }
-      } else {
-        k = 1;
-        const int g = f - G::NFX;
-        const int fy = g / TX;
-        la = g % TX;
-        lay = fy - 1;
-        lb_x = la;
-        lb_y = fy;
-        const int gface = y0 + fy;
-        if ((!c.py && (gface == 0 || gface >= ny)) || gface > ny) {
-          sfy[0][g] = 0.0;
-          sfy[1][g] = 0.0;
-          continue;
-        }
+    double* F0 = (K == 0) ? sfx[0] : sfy[0];
+    double* F1 = (K == 0) ? sfx[1] : sfy[1];
+    for (int f = tid; f < NF; f += G::NT) {
+      const int fa = f % RW, fb = f / RW;
+      // cell a = (ax, ay), cell b = a + e_K
+      const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
+      const int bx = (K == 0) ? fa : fa, by = (K == 0) ? fb : fb;
+      const int gface = (K == 0) ? x0 + fa : y0 + fb;
+      const int nk = (K == 0) ? nx : ny;
+      const int pk = (K == 0) ? c.px : c.py;
+      if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
+        F0[f] = 0.0;
+        F1[f] = 0.0;
+        continue;
       }
-      const int ia = G::i2(la, lay), ib = G::i2(lb_x, lb_y);
-      const int ja = G::i1(la, lay), jb = G::i1(lb_x, lb_y);
+      const int ia = G::i2(ax, ay), ib = G::i2(bx, by);
+      const int ja = G::i1(ax, ay), jb = G::i1(bx, by);
       double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
       const double pa = su[s0][0][ia], pb = su[s0][0][ib];
       const double ca = su[s0][1][ia], cb = su[s0][1][ib];
       const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
-      gph[k] = (pb - pa) * c.inv_dx;
-      gmu[k] = (smu[m0][jb] - smu[m0][ja]) * c.inv_dx;
-      gcs[k] = (cb - ca) * c.inv_dx;
-      gcl[k] = (lb_ - la_) * c.inv_dx;
-      // transverse in-plane axis (3D only): the other of x/y
-      if (DIM == 3) {
-        const int j = 1 - k;
-        const int d2 = (j == 0) ? 1 : G::BX2;
-        const int d1 = (j == 0) ? 1 : G::BX1;
-        gph[j] = 0.5 * ((su[s0][0][ia + d2] - su[s0][0][ia - d2]) * c.inv_2dx +
-                        (su[s0][0][ib + d2] - su[s0][0][ib - d2]) * c.inv_2dx);
-        gmu[j] = 0.5 * ((smu[m0][ja + d1] - smu[m0][ja - d1]) * c.inv_2dx +
-                        (smu[m0][jb + d1] - smu[m0][jb - d1]) * c.inv_2dx);
-        gcs[j] = 0.5 * ((su[s0][1][ia + d2] - su[s0][1][ia - d2]) * c.inv_2dx +
-                        (su[s0][1][ib + d2] - su[s0][1][ib - d2]) * c.inv_2dx);
-        gcl[j] = 0.5 * ((su[s0][2][ia + d2] - su[s0][2][ia - d2]) * c.inv_2dx +
-                        (su[s0][2][ib + d2] - su[s0][2][ib - d2]) * c.inv_2dx);
+      gph[K] = (pb - pa) * c.inv_dx;
+      gmu[K] = (smu[m0][jb] - smu[m0][ja]) * c.inv_dx;
+      gcs[K] = (cb - ca) * c.inv_dx;
+      gcl[K] = (lb_ - la_) * c.inv_dx;
+      if (DIM == 3) {  // the other in-plane axis
+        constexpr int J = 1 - K;
+        constexpr int d2 = (J == 0) ? 1 : G::BX2;
+        constexpr int d1 = (J == 0) ? 1 : G::BX1;
+        gph[J] = ((su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2])) * c.inv_4dx;
+        gmu[J] = ((smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1])) * c.inv_4dx;
+        gcs[J] = ((su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2])) * c.inv_4dx;
+        gcl[J] = ((su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2])) * c.inv_4dx;
       }
-      // transverse z
-      const int kz = DIM - 1;
-      gph[kz] = 0.5 * ((su[sp][0][ia] - su[sm][0][ia]) * c.inv_2dx + (su[sp][0][ib] - su[sm][0][ib]) * c.inv_2dx);
-      gmu[kz] = 0.5 * ((smu[mp][ja] - smu[mm][ja]) * c.inv_2dx + (smu[mp][jb] - smu[mm][jb]) * c.inv_2dx);
-      gcs[kz] = 0.5 * ((su[sp][1][ia] - su[sm][1][ia]) * c.inv_2dx + (su[sp][1][ib] - su[sm][1][ib]) * c.inv_2dx);
-      gcl[kz] = 0.5 * ((su[sp][2][ia] - su[sm][2][ia]) * c.inv_2dx + (su[sp][2][ib] - su[sm][2][ib]) * c.inv_2dx);
+      constexpr int kz = DIM - 1;  // transverse z
+      gph[kz] = ((su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib])) * c.inv_4dx;
+      gmu[kz] = ((smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb])) * c.inv_4dx;
+      gcs[kz] = ((su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib])) * c.inv_4dx;
+      gcl[kz] = ((su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib])) * c.inv_4dx;
       const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
       double Fs, Fl;
-      face_flux<DIM>(c, k, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
-      if (k == 0) {
-        sfx[0][f] = Fs;
-        sfx[1][f] = Fl;
-      } else {
-        sfy[0][f - G::NFX] = Fs;
-        sfy[1][f - G::NFX] = Fl;
-      }
+      face_flux<DIM, K>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+      F0[f] = Fs;
+      F1[f] = Fl;
     }
   };
 
@@ -272,7 +246,8 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     __syncthreads();
     cell_plane(z + 1);
     __syncthreads();
-    xy_faces(z);
+    inplane_faces(std::integral_constant<int, 0>{}, z);
+    if constexpr (DIM == 3) inplane_faces(std::integral_constant<int, 1>{}, z);
     double FsU, FlU;
     zface(z, FsU, FlU);
     __syncthreads();
@@ -460,47 +435,56 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
     const double lMU = at_lo ? 0.0 : xd[1][1][t - 1];
     const double rPT = has_right ? xd[0][0][t + 1] : 0.0;
     const double rMU = has_right ? xd[0][1][t + 1] : 0.0;
-    // faces j = 0..cnt: face j lies between local cells j-1 and j
-    double FS[R1_CMAX + 1], FL[R1_CMAX + 1];
+    // Faces j = 0..cnt lie between local cells j-1 and j (mirror ends have zero
+    // flux).  Rolling over the cells: face j+1 is computed before cell j is
+    // updated, so no face array is kept.
+    auto face = [&](int j, double& Fs, double& Fl) {
+      Fs = 0.0;
+      Fl = 0.0;
+      if (cnt <= 0 || (j == 0 && at_lo) || (j == cnt && at_hi)) return;
+      double pa = lP, sa = lS, la = lL, ta = lPT, ma = lMU;
+      double pb = rP, sb = rS, lb = rL, tb = rPT, mb = rMU;
 #pragma unroll
-    for (int j = 0; j <= R1_CMAX; ++j) {
-      FS[j] = 0.0;
-      FL[j] = 0.0;
-      if (cnt > 0 && j <= cnt) {
-        const bool boundary = (j == 0 && at_lo) || (j == cnt && at_hi);
-        if (!boundary) {
-          const double pa = (j == 0) ? lP : P[(j > 0 ? j : 1) - 1];
-          const double sa = (j == 0) ? lS : S[(j > 0 ? j : 1) - 1];
-          const double la = (j == 0) ? lL : L[(j > 0 ? j : 1) - 1];
-          const double ta = (j == 0) ? lPT : PT[(j > 0 ? j : 1) - 1];
-          const double ma = (j == 0) ? lMU : MU[(j > 0 ? j : 1) - 1];
-          const double pb = (j == cnt) ? rP : P[(j < R1_CMAX) ? j : R1_CMAX - 1];
-          const double sb = (j == cnt) ? rS : S[(j < R1_CMAX) ? j : R1_CMAX - 1];
-          const double lb = (j == cnt) ? rL : L[(j < R1_CMAX) ? j : R1_CMAX - 1];
-          const double tb = (j == cnt) ? rPT : PT[(j < R1_CMAX) ? j : R1_CMAX - 1];
-          const double mb = (j == cnt) ? rMU : MU[(j < R1_CMAX) ? j : R1_CMAX - 1];
-          double g0[1] = {(pb - pa) * c.inv_dx};
-          double g1[1] = {(mb - ma) * c.inv_dx};
-          double g2[1] = {(sb - sa) * c.inv_dx};
-          double g3[1] = {(lb - la) * c.inv_dx};
-          face_flux<1>(c, 0, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3,
-                       FS[j], FL[j]);
+      for (int k = 0; k < R1_CMAX; ++k) {
+        if (k == j - 1) {
+          pa = P[k];
+          sa = S[k];
+          la = L[k];
+          ta = PT[k];
+          ma = MU[k];
+        }
+        if (k == j && j < cnt) {
+          pb = P[k];
+          sb = S[k];
+          lb = L[k];
+          tb = PT[k];
+          mb = MU[k];
         }
       }
-    }
-    // update
+      double g0[1] = {(pb - pa) * c.inv_dx};
+      double g1[1] = {(mb - ma) * c.inv_dx};
+      double g2[1] = {(sb - sa) * c.inv_dx};
+      double g3[1] = {(lb - la) * c.inv_dx};
+      face_flux<1, 0>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3, Fs, Fl);
+    };
+    double FsL, FlL;
+    face(0, FsL, FlL);
 #pragma unroll
     for (int k = 0; k < R1_CMAX; ++k) {
       if (k < cnt) {
+        double FsR, FlR;
+        face(k + 1, FsR, FlR);
         double p, q, dp;
         interp(c, P[k], p, q, dp);
         const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
-        const double ns = S[k] + dt * ((FS[k + 1] - FS[k]) * c.inv_dx + src);
-        const double nl = L[k] + dt * ((FL[k + 1] - FL[k]) * c.inv_dx + src);
+        const double ns = S[k] + dt * ((FsR - FsL) * c.inv_dx + src);
+        const double nl = L[k] + dt * ((FlR - FlL) * c.inv_dx + src);
         P[k] = P[k] + dt * PT[k];
         S[k] = ns;
         L[k] = nl;
         errbits |= check_bits(P[k], S[k], L[k]);
+        FsL = FsR;
+        FlL = FlR;
       }
     }
     if (shift) {  // uniform across the workgroup

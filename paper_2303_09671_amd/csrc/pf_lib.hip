@@ -64,8 +64,10 @@ struct pf_handle {
   pfk::Partial* d_part = nullptr;
   pfk::Partial* d_runred = nullptr;
   double* d_dldk = nullptr;
-  double* d_theta_part = nullptr;  // adjoint partials
+  double* d_theta_part = nullptr;  // adjoint: per-block parameter cotangents
   int ntheta_part = 0;
+  pfadj::Tile1* d_tiles = nullptr;   // adjoint: (run, tile) table of 1D runs
+  int ntiles = 0;
   int* d_err = nullptr;
   long long n = 0;  // step counter
 
@@ -173,6 +175,7 @@ pfk::Const make_const(const pf_params& p) {
   c.dx = p.dx;
   c.inv_dx = 1.0 / p.dx;
   c.inv_2dx = 1.0 / (2.0 * p.dx);
+  c.inv_4dx = 1.0 / (4.0 * p.dx);
   c.inv_dx2 = 1.0 / (p.dx * p.dx);
   c.dt = p.dt;
   c.W = p.W;
@@ -504,10 +507,52 @@ int pf_kv_seed(pf_handle* h, const double* dL_dk, double* const lam[3]) {
 int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
                     double* const lam_n[3], double* dtheta) {
   if (!h || !u_n || !lam_np1 || !lam_n || !dtheta || n < 0) return fail(PF_EINVAL, "null argument");
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 3; ++k) {
     if (!u_n[k] || !lam_np1[k] || !lam_n[k]) return fail(PF_EINVAL, "null field pointer");
-  return pfadj::adjoint_step(h->c, h->batched, h->nrun, h->runtab(), h->p.shift, n, u_n, lam_np1, lam_n, dtheta,
-                             h->stream, &h->d_theta_part, &h->ntheta_part, g_detail);
+    for (int j = 0; j < 3; ++j)
+      if (lam_n[k] == lam_np1[j]) return fail(PF_EINVAL, "lam_n may not alias lam_np1");
+  }
+  const pfk::Const& c = h->c;
+  int nblk = 0;
+  if (h->batched) {
+    if (!h->d_tiles) {
+      std::vector<pfadj::Tile1> tiles;
+      for (int r = 0; r < h->nrun; ++r)
+        for (int z = 0; z < h->h_n[r]; z += pfadj::Geo<1>::TZ) tiles.push_back(pfadj::Tile1{r, z});
+      int rc = upload(&h->d_tiles, tiles, h->stream);
+      if (rc) return rc;
+      h->ntiles = (int)tiles.size();
+    }
+    nblk = h->ntiles;
+  } else if (c.dim == 2) {
+    if (c.px && c.nx < pfadj::Geo<2>::TX + 2 * pfadj::H)
+      return fail(PF_EINVAL, "adjoint: a periodic x axis needs nx >= 22");
+    nblk = ((c.nx + pfadj::Geo<2>::TX - 1) / pfadj::Geo<2>::TX) * ((c.nz + pfadj::Geo<2>::TZ - 1) / pfadj::Geo<2>::TZ);
+  } else {
+    return fail(PF_EINVAL, "adjoint step is built for 1D runs and 2D grids");
+  }
+  if (nblk > h->ntheta_part) {
+    if (h->d_theta_part) (void)hipFree(h->d_theta_part);
+    h->d_theta_part = nullptr;
+    int rc = dalloc(&h->d_theta_part, (size_t)nblk * 4);
+    if (rc) return rc;
+    h->ntheta_part = nblk;
+  }
+  if (h->batched) {
+    hipLaunchKernelGGL(pfadj::k_adj1d, dim3(nblk), dim3(256), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n,
+                       h->p.shift, u_n[0], u_n[1], u_n[2], lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1],
+                       lam_n[2], h->d_theta_part);
+  } else {
+    const double tn = (double)n * c.dt;
+    const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > std::floor(c.V * tn / c.dx));
+    dim3 grid((c.nx + pfadj::Geo<2>::TX - 1) / pfadj::Geo<2>::TX, (c.nz + pfadj::Geo<2>::TZ - 1) / pfadj::Geo<2>::TZ);
+    hipLaunchKernelGGL(pfadj::k_adj2d, grid, dim3(256), 0, h->stream, c, (long long)n, sh, u_n[0], u_n[1], u_n[2],
+                       lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2], h->d_theta_part);
+  }
+  PF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pfadj::k_theta_final, dim3(1), dim3(256), 0, h->stream, c, h->d_theta_part, nblk, dtheta);
+  PF_HIP(hipGetLastError());
+  return PF_OK;
 }
 
 void pf_destroy(pf_handle* h) {
@@ -529,6 +574,7 @@ void pf_destroy(pf_handle* h) {
   (void)hipFree(h->d_runred);
   (void)hipFree(h->d_dldk);
   (void)hipFree(h->d_theta_part);
+  (void)hipFree(h->d_tiles);
   (void)hipFree(h->d_err);
   delete h;
 }
