@@ -111,6 +111,28 @@ def bench_batch(torch, pf, steps):
                 speedup=t_seq / t_batch, cell_updates_per_s=cells * steps / t_batch)
 
 
+def bench_adjoint(torch, nsteps=2000):
+    """Adjoint/forward step-time ratio on the adjoint fit workloads (64 1D runs
+    N = 2048; 2D 512^2), over nsteps with checkpoints every 100 steps: forward
+    pass with checkpoints vs backward (segment replay + adjoint steps)."""
+    from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd.adjoint import Workload, adjoint_only_seconds, forward_k
+    one_d, two_d, _, _ = I.adjoint_workloads()
+    res = {}
+    for name, args in (("1d_64x2048", one_d), ("2d_512x512", two_d)):
+        wl = Workload(**dict(args, nsteps=nsteps))
+        theta = (wl.params["A"], wl.params["Mphi"], wl.params["W"])
+        forward_k(wl, theta)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        forward_k(wl, theta, checkpoints=True)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        tb = adjoint_only_seconds(wl, theta)
+        res[name] = dict(steps=nsteps, forward_s=tf, backward_s=tb, ratio=tb / tf)
+    return res
+
+
 def cpu_baseline(p, pert):
     from oracle import oracle as O
     from paper_2303_09671_amd import inputs as I
@@ -208,6 +230,7 @@ def main():
         _, cm, _ = pf.pf_solute(h1)
         extra["1d_1024_20000_steps"] = dict(seconds=d1, cell_updates_per_s=1024 * steps1 / d1, k=float(1.0 / cm[0]))
         extra["batch_256_runs"] = bench_batch(torch, pf, 2000)
+        extra["adjoint"] = bench_adjoint(torch)
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -27,6 +27,9 @@
 //   * second-order central gradients at cells, compact Laplacian, staggered
 //     fluxes with mobilities / anti-trapping evaluated at the face centre from
 //     face means, forward Euler (Sec. V.A);
+//   * 1/|grad phi|^2 (normal projection, anti-trapping, the phi prefactor) is
+//     regularised as G / (G^2 + eps^2), G = |grad phi|^2: 1/G wherever G >> eps,
+//     a smooth decay to 0 where the gradient vanishes (the paper is silent);
 //   * the moving window: when floor(V t_{n+1}/dx) exceeds the shift count the
 //     cold-end layer is dropped and a fresh liquid layer (phi=0, c_l=1,
 //     c_s=k_e) is appended at the hot end (Sec. V.A, shifting algorithm);
@@ -90,7 +93,7 @@ struct OrcParams {
   double inv_lT;   // 1 / thermal length (0 = isothermal at T_s)
   double V;        // pulling speed
   double z0;       // initial interface position (lab frame)
-  double eps_grad; // |grad phi|^2 gate
+  double eps_grad; // scale of the smooth |grad phi|^2 gate
 };
 
 // Parameters promoted to the working scalar type; theta = (A, Mphi, W) may carry tangents.
@@ -245,7 +248,7 @@ T phi_t_at(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, cons
   }
   T G = 0.0;
   for (int k = 0; k < P.dim; ++k) G = G + gphi[k] * gphi[k];
-  T gam = (val(G) > P.eps_grad) ? T(1.0) / G : T(0.0);  // 1/|grad phi|^2, gated
+  T gam = G / (G * G + P.eps_grad * P.eps_grad);  // 1/|grad phi|^2, smoothly gated below eps_grad
   T pq = q.p * q.q;
   T onemA = 1.0 - w.A;
   // Prefactor: 1/M_phi + (c_s-c_l)^2 (1-A)^2 b p(1-p) / (Mbar (b p + 1 - p)) / |grad phi|^2
@@ -303,7 +306,7 @@ bool face_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, 
     dcs = dcs + grad[0][j] * grad[2][j];
     dcl = dcl + grad[0][j] * grad[3][j];
   }
-  T gam = (val(G) > P.eps_grad) ? T(1.0) / G : T(0.0);
+  T gam = G / (G * G + P.eps_grad * P.eps_grad);  // smooth gate, as at cells
   // Normal projection n n^T grad u = gam (grad phi . grad u) grad phi; k-components:
   T n_mubar = gam * dmu * grad[0][k];
   T t_cs = grad[2][k] - gam * dcs * grad[0][k];

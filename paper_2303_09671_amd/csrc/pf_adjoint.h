@@ -228,9 +228,9 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       }
       const double Ms = c.Ds * csf, Ml = clf;
       const double ms = Ms * q, ml = c.b * Ml * p, Mb = ms + ml;
-      const bool on = Gs > c.eps_grad;
-      const double iMG = on ? 1.0 / (Mb * Gs) : 0.0;
-      const double R = gph[K] * iMG;
+      const double Sg = Gs * Gs + c.eps2;
+      const double iMS = 1.0 / (Mb * Sg);
+      const double R = gph[K] * Gs * iMS;  // (grad phi)_K gam / Mbar, gam = G / (G^2 + eps^2)
       const double bq = c.b * p + q;
       const double dcf = csf - clf;
       const double at = c.onemA * dcf * ptf * R;
@@ -265,13 +265,10 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       R_b += nrm_b * Ms * Ml * bq * dmu;
       p_b += bq_b * c.b;
       q_b += bq_b;
-      // R = gph[K] / (Mb G)
-      double Gs_b = 0.0;
-      if (on) {
-        gph_b[K] += R_b * iMG;
-        Mb_b += -R_b * R / Mb;
-        Gs_b += -R_b * R / Gs;
-      }
+      // R = gph[K] G / (Mb S), S = G^2 + eps^2
+      double Gs_b = R_b * gph[K] * iMS - R_b * R * 2.0 * Gs / Sg;
+      gph_b[K] += R_b * Gs * iMS;
+      Mb_b += -R_b * R / Mb;
       ms_b += Mb_b;
       ml_b += Mb_b;
       Ms_b += ms_b * q;
@@ -344,8 +341,8 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double gph[DIM], gcs[DIM], gcl[DIM], lap;
     cell_inputs(i, gph, gcs, gcl, lap);
     const double cleq = cleq_of_lz(lz);
-    const double ll = log(cl);
-    const double dmu = log(cs) - ll - c.log_ke;
+    const double ll = pfk::flog(cl);
+    const double dmu = pfk::flog(cs) - ll - c.log_ke;
     const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;
     const double ms = c.Ds * cs * q, ml = c.b * cl * p, Mb = ms + ml;
     const double Dn = ms * (1.0 - c.A * q) + c.A * ml * p;
@@ -355,17 +352,16 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       Gs += gph[k] * gph[k];
       dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
     }
-    const bool on = Gs > c.eps_grad;
+    const double Sg = Gs * Gs + c.eps2;
     const double bq = c.b * p + q;
-    const double Gp = on ? Gs * bq : 1.0;
-    const double Q = Mb * Gp;
+    const double Q = Mb * bq * Sg;
     const double pq = p * q;
     const double oA = c.onemA;
     const double fdw = 2.0 * ph * (1.0 - ph) * (1.0 - 2.0 * ph);
     const double base = c.W2 * lap - fdw - c.lambda * dGc * dp;
-    const double X2 = Dn * dc * dmu * dp * Gp;
-    const double X3 = on ? oA * dc * pq * dot * bq : 0.0;
-    const double Kd = on ? oA * oA * c.b * dc * dc * pq : 0.0;
+    const double X2 = Dn * dc * dmu * dp * bq * Sg;
+    const double X3 = oA * dc * pq * dot * Gs * bq;
+    const double Kd = oA * oA * c.b * dc * dc * pq * Gs;
     const double num = base * Q + c.lambda * X2 + c.lambda * X3;
     const double den = c.alpha * Q + c.lambda * Kd;
     const double iden = 1.0 / den;
@@ -376,27 +372,32 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       thAl += den_b * Q;
       thLa += den_b * Kd + num_b * (X2 + X3);
     }
-    double dc_b = 0.0, pq_b = 0.0, dot_b = 0.0, bq_b = 0.0, p_b = 0.0, q_b = 0.0, Gs_b = 0.0, Gp_b = 0.0;
+    double dc_b = 0.0, pq_b = 0.0, dot_b = 0.0, bq_b = 0.0, p_b = 0.0, q_b = 0.0, Gs_b = 0.0, Sg_b = 0.0;
     double dmu_b = 0.0, dp_b = 0.0, Dn_b = 0.0, Mb_b = 0.0, ms_b = 0.0, ml_b = 0.0, lap_b = 0.0;
-    if (on) {  // Kd = (1-A)^2 b dc^2 pq,  X3 = (1-A) dc pq dot bq
+    {  // Kd = (1-A)^2 b dc^2 pq G
       const double Kd_b = den_b * c.lambda;
-      if (own) thA += Kd_b * (-2.0 * oA * c.b * dc * dc * pq);
-      dc_b += Kd_b * 2.0 * oA * oA * c.b * dc * pq;
-      pq_b += Kd_b * oA * oA * c.b * dc * dc;
-      const double X3_b = num_b * c.lambda;
-      if (own) thA += X3_b * (-dc * pq * dot * bq);
-      dc_b += X3_b * oA * pq * dot * bq;
-      pq_b += X3_b * oA * dc * dot * bq;
-      dot_b += X3_b * oA * dc * pq * bq;
-      bq_b += X3_b * oA * dc * pq * dot;
+      if (own) thA += Kd_b * (-2.0 * oA * c.b * dc * dc * pq * Gs);
+      dc_b += Kd_b * 2.0 * oA * oA * c.b * dc * pq * Gs;
+      pq_b += Kd_b * oA * oA * c.b * dc * dc * Gs;
+      Gs_b += Kd_b * oA * oA * c.b * dc * dc * pq;
     }
-    {  // X2 = Dn dc dmu dp Gp
+    {  // X3 = (1-A) dc pq dot G bq
+      const double X3_b = num_b * c.lambda;
+      if (own) thA += X3_b * (-dc * pq * dot * Gs * bq);
+      dc_b += X3_b * oA * pq * dot * Gs * bq;
+      pq_b += X3_b * oA * dc * dot * Gs * bq;
+      dot_b += X3_b * oA * dc * pq * Gs * bq;
+      Gs_b += X3_b * oA * dc * pq * dot * bq;
+      bq_b += X3_b * oA * dc * pq * dot * Gs;
+    }
+    {  // X2 = Dn dc dmu dp bq S
       const double X2_b = num_b * c.lambda;
-      Dn_b += X2_b * dc * dmu * dp * Gp;
-      dc_b += X2_b * Dn * dmu * dp * Gp;
-      dmu_b += X2_b * Dn * dc * dp * Gp;
-      dp_b += X2_b * Dn * dc * dmu * Gp;
-      Gp_b += X2_b * Dn * dc * dmu * dp;
+      Dn_b += X2_b * dc * dmu * dp * bq * Sg;
+      dc_b += X2_b * Dn * dmu * dp * bq * Sg;
+      dmu_b += X2_b * Dn * dc * dp * bq * Sg;
+      dp_b += X2_b * Dn * dc * dmu * bq * Sg;
+      bq_b += X2_b * Dn * dc * dmu * dp * Sg;
+      Sg_b += X2_b * Dn * dc * dmu * dp * bq;
     }
     {  // base = W2 lap - fdw - lambda dGc dp
       const double base_b = num_b * Q;
@@ -412,12 +413,11 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       dmu_b += dGc_b * cs;
       dc_b += -dGc_b;
     }
-    Mb_b += Q_b * Gp;
-    Gp_b += Q_b * Mb;
-    if (on) {
-      Gs_b += Gp_b * bq;
-      bq_b += Gp_b * Gs;
-    }
+    // Q = Mb bq S, S = G^2 + eps^2
+    Mb_b += Q_b * bq * Sg;
+    bq_b += Q_b * Mb * Sg;
+    Sg_b += Q_b * Mb * bq;
+    Gs_b += Sg_b * 2.0 * Gs;
     p_b += pq_b * q + bq_b * c.b;
     q_b += pq_b * p + bq_b;
     // Dn = ms (1 - A q) + A ml p
@@ -469,7 +469,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double p, q, dp;
     pfk::interp(c, ph, p, q, dp);
     const double mb = amu[i];
-    const double dmu = log(cs) - log(cl) - c.log_ke;
+    const double dmu = pfk::flog(cs) - pfk::flog(cl) - c.log_ke;
     // mu_bar = ln cl + p dmu
     const double r0 = sl[0][i] + au[0][i] + mb * dmu * dp;
     const double r1 = sl[1][i] + au[1][i] + mb * p / cs;

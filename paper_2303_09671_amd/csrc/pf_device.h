@@ -23,7 +23,7 @@ struct Const {
   // model
   double dx, inv_dx, inv_2dx, inv_4dx, inv_dx2, dt;
   double W, W2, alpha, lambda, lambda0, Mphi;
-  double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad;
+  double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad, eps2;
 };
 
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
@@ -34,6 +34,38 @@ __device__ __forceinline__ double frcp(double x) {
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
+}
+
+// Natural logarithm for positive normal x, within 2 ulp: x = 2^e m with
+// m in [1/sqrt 2, sqrt 2), ln x = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1),
+// 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ... + s^22/23) (|s| <= 0.1716, the
+// series tail is below 1e-17).  NaN for x <= 0 or NaN.
+__device__ __forceinline__ double flog(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double s = (m - 1.0) * frcp(m + 1.0);
+  const double s2 = s * s;
+  double t = 1.0 / 23.0;
+  t = __builtin_fma(t, s2, 1.0 / 21.0);
+  t = __builtin_fma(t, s2, 1.0 / 19.0);
+  t = __builtin_fma(t, s2, 1.0 / 17.0);
+  t = __builtin_fma(t, s2, 1.0 / 15.0);
+  t = __builtin_fma(t, s2, 1.0 / 13.0);
+  t = __builtin_fma(t, s2, 1.0 / 11.0);
+  t = __builtin_fma(t, s2, 1.0 / 9.0);
+  t = __builtin_fma(t, s2, 1.0 / 7.0);
+  t = __builtin_fma(t, s2, 1.0 / 5.0);
+  t = __builtin_fma(t, s2, 1.0 / 3.0);
+  const double s_2 = s + s;
+  const double lm = __builtin_fma(s_2 * s2, t, s_2);
+  const double ed = (double)e;
+  const double ln2_hi = 6.93147180369123816490e-01;  // ln 2 truncated to 32 significant bits (e ln2_hi exact)
+  const double ln2_lo = 1.90821492927058770002e-10;  // ln 2 - ln2_hi (from 2 atanh(1/3))
+  const double r = __builtin_fma(ed, ln2_hi, __builtin_fma(ed, ln2_lo, lm));
+  return (x > 0.0) ? r : __builtin_nan("");
 }
 
 // Interpolation p(phi) = h + a_p (phi - 1/2) phi^2 (1-phi)^2 (Eq. interpolation2),
@@ -85,28 +117,29 @@ __device__ __forceinline__ double cleq_at(const Const& c, double zlab, double t,
 __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs, double cl) {
   double p, q;
   interp_pq(c, phi, p, q);
-  const double ll = log(cl);
-  return ll + p * (log(cs) - ll - c.log_ke);
+  const double ll = flog(cl);
+  return ll + p * (flog(cs) - ll - c.log_ke);
 }
 
 // Cell stage: phi_t (Eq. phasefield_nonvar divided by H) and mu_bar.
 //   g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
 //   compact Laplacian of phi.
-// With Mbar = M_s(1-p) + b M_l p, G = |grad phi|^2 and the drag numerator
+// With Mbar = M_s(1-p) + b M_l p, G = |grad phi|^2, the regularised inverse
+// gam = G / S, S = G^2 + eps^2, and the drag numerator
 // Dn = M_s(1-p)(1 - A(1-p)) + A b M_l p^2 (drag D = Dn / Mbar), the rate
 //   phi_t = [W^2 lap - f' - lambda (dG_c - D dc dmu) p' + X] / tau,
-//   X   = lambda (1-A) dc p(1-p) (Ds grad c_s - b grad c_l).grad phi / (Mbar G),
-//   tau = alpha + lambda (1-A)^2 dc^2 b p(1-p) / (Mbar G (b p + 1 - p)),
-// is evaluated with numerator and prefactor multiplied by Q = Mbar G (b p + 1 - p)
-// (by Mbar alone below the gate, where X = 0 and tau = alpha): one division.
+//   X   = lambda (1-A) dc p(1-p) (Ds grad c_s - b grad c_l).grad phi gam / Mbar,
+//   tau = alpha + lambda (1-A)^2 dc^2 b p(1-p) gam / (Mbar (b p + 1 - p)),
+// is evaluated with numerator and prefactor multiplied by Q = Mbar (b p + 1 - p) S:
+// one reciprocal.
 template <int DIM>
 __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
                                            const double* gph, const double* gcs, const double* gcl,
                                            double lap, double& phit, double& mubar) {
   double p, q, dp;
   interp(c, phi, p, q, dp);
-  const double ll = log(cl);
-  const double dmu = log(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
+  const double ll = flog(cl);
+  const double dmu = flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
   mubar = ll + p * dmu;
   const double dc = cs - cl;
   const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;  // Eq. dil5.2 with Eq. ds3
@@ -120,27 +153,26 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
     G += gph[k] * gph[k];
     dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
   }
-  const bool on = G > c.eps_grad;
+  const double S = G * G + c.eps2;
   const double bq = c.b * p + q;
-  const double Gp = on ? G * bq : 1.0;
-  const double Q = Mb * Gp;
+  const double Q = Mb * bq * S;
   const double pq = p * q;
   const double lAdc = c.lambda * c.onemA * dc;
   const double fdw = 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
   const double base = c.W2 * lap - fdw - c.lambda * dGc * dp;
-  const double num = base * Q + c.lambda * Dn * dc * dmu * dp * Gp + (on ? lAdc * pq * dot * bq : 0.0);
-  const double den = c.alpha * Q + (on ? lAdc * c.onemA * dc * c.b * pq : 0.0);
+  const double num = base * Q + c.lambda * Dn * dc * dmu * dp * bq * S + lAdc * pq * dot * G * bq;
+  const double den = c.alpha * Q + lAdc * c.onemA * dc * c.b * pq * G;
   phit = num * frcp(den);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
 // through a face normal to axis K.  phf, csf, clf, ptf are the face means;
 // g*[j] the face gradient (compact along K, mean of central differences
-// across K) of phi, mu_bar, c_s, c_l.  With R = (grad phi)_K / (Mbar G):
+// across K) of phi, mu_bar, c_s, c_l.  With gam = G/(G^2 + eps^2) (regularised
+// 1/|grad phi|^2) and R = (grad phi)_K gam / Mbar:
 //   q_n (n n^T grad mu_bar)_K = M_s M_l (b p + 1 - p) (grad phi . grad mu_bar) R,
 //   ((1 - n n^T) grad c)_K    = (grad c)_K - (grad phi . grad c) Mbar R,
-//   anti-trapping_s / _l      = +/- (1-A)(c_s - c_l) phi_t R M_s(1-p) / b M_l p;
-// below the gate R = 0 and only the tangential parts remain.
+//   anti-trapping_s / _l      = +/- (1-A)(c_s - c_l) phi_t R M_s(1-p) / b M_l p.
 template <int DIM, int K>
 __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf, double clf, double ptf,
                                           const double* gph, const double* gmu, const double* gcs,
@@ -159,7 +191,7 @@ __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf
   const double Ml = clf;
   const double ms = Ms * q, ml = c.b * Ml * p;
   const double Mb = ms + ml;
-  const double R = (G > c.eps_grad) ? gph[K] * frcp(Mb * G) : 0.0;
+  const double R = gph[K] * G * frcp(Mb * (G * G + c.eps2));
   const double nrm = Ms * Ml * (c.b * p + q) * dmu * R;
   const double at = c.onemA * (csf - clf) * ptf * R;
   Fs = nrm + c.Ds * (gcs[K] - dcs * Mb * R) + at * ms;

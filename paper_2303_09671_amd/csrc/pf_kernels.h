@@ -85,18 +85,31 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
   const int gxo = x0 + ox, gyo = y0 + oy;
   const bool own_valid = (gxo < nx) && (gyo < ny);
 
+  // In-plane global offsets of this thread's ring positions (the same for
+  // every plane): computed once, so a plane load is three loads per position.
+  constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
+  long long ld_off[NLD];
+#pragma unroll
+  for (int r = 0; r < NLD; ++r) {
+    const int i = tid + r * G::NT;
+    const int lx = i % G::BX2 - 2;
+    const int ly = i / G::BX2 - G::OY2;
+    const int gx = map_axis(x0 + lx, nx, c.px);
+    const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
+    ld_off[r] = (long long)gx + (long long)nx * gy;
+  }
   auto load_plane = [&](int gz) {
     const int slot = (gz + 8) & 3;
-    const int zm = mirror_idx(gz, nz);
-    for (int i = tid; i < G::P2; i += G::NT) {
-      const int lx = i % G::BX2 - 2;
-      const int ly = i / G::BX2 - G::OY2;
-      const int gx = map_axis(x0 + lx, nx, c.px);
-      const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
-      const long long idx = (long long)gx + (long long)nx * gy + plane * zm;
-      su[slot][0][i] = iph[idx];
-      su[slot][1][i] = ics[idx];
-      su[slot][2][i] = icl[idx];
+    const long long zo = plane * mirror_idx(gz, nz);
+#pragma unroll
+    for (int r = 0; r < NLD; ++r) {
+      const int i = tid + r * G::NT;
+      if (i < G::P2) {
+        const long long idx = ld_off[r] + zo;
+        su[slot][0][i] = iph[idx];
+        su[slot][1][i] = ics[idx];
+        su[slot][2][i] = icl[idx];
+      }
     }
   };
 
@@ -586,8 +599,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_chunks(Const c, RunTab r
     interp_pq(c, f, p, q);
     const double zlab = ((double)z + sn + 0.5) * c.dx;
     const double cleq = cleq_at(c, zlab, tn, V, z0);
-    const double fs = a * log(a) - a - a * c.log_ke + (c.ke - 1.0) * cleq;
-    const double fl = b * log(b) - b;
+    const double fs = a * flog(a) - a - a * c.log_ke + (c.ke - 1.0) * cleq;
+    const double fl = b * flog(b) - b;
     const double w = f * (1.0 - f);
     double en = w * w + c.lambda * (p * fs + q * fl);
     // gradient energy on the faces above the cell (each face once)

@@ -195,6 +195,7 @@ pfk::Const make_const(const pf_params& p) {
   c.V = p.V;
   c.z0 = p.z0;
   c.eps_grad = p.eps_grad;
+  c.eps2 = p.eps_grad * p.eps_grad;
   return c;
 }
 

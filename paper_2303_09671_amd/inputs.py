@@ -147,3 +147,21 @@ def batch_fields(runs, ke: float = ALLOY["ke"], W: float = 1.0, align: int = 32)
         cs[o:o + r["N"]] = s
         cl[o:o + r["N"]] = l
     return phi, cs, cl, np.asarray(offs, dtype=np.int64)
+
+
+def adjoint_workloads():
+    """The adjoint fit workload: (1D batch workload args, 2D workload args,
+    per-run targets, 2D target).  64 runs N = 2048 with V log-spaced in
+    [1e-2, 1], one 2D 512^2 run at V = 0.05 (dt = 0.032, seeded 1e-3 front
+    perturbation), 10000 steps, checkpoints every 100 steps."""
+    runs, VD = adjoint_runs()
+    base = base_params(dim=1)
+    phi, cs, cl, offs = batch_fields(runs)
+    one_d = dict(params=base, fields0=(phi, cs, cl), nsteps=10000, every=100, runs=runs, offsets=offs)
+    p2, _, pert = config_2d(nx=512, nz=512, seed=5)
+    f2 = tuple(a.ravel() for a in planar_front(2, p2["n"], p2["dx"], p2["z0"], p2["ke"], amp=pert["amp"],
+                                                 seed=pert["seed"]))
+    two_d = dict(params=p2, fields0=f2, nsteps=10000, every=100)
+    ke = ALLOY["ke"]
+    k2 = (ke + p2["V"] / VD) / (1.0 + p2["V"] / VD)
+    return one_d, two_d, [r["k_target"] for r in runs], k2

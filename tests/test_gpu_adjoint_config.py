@@ -1,0 +1,54 @@
+"""The adjoint fit workload at its configured size: 64 1D runs (N = 2048, V
+log-spaced 1e-2..1) plus one 2D 512^2 run, 10000 steps, checkpoints every 100
+steps; loss L = sum (k - k*)^2 against the seeded Aziz-form target curve.
+dL/dtheta, theta = (A, M_phi, W), from the adjoint must agree with central
+finite differences to 1e-5 relative; the argmax cell of every run must not move
+between the +h and -h runs (max() is differentiated through it).
+
+Checked at h = 1e-6 (the configured step) and h = 1e-8.  Both need the step
+map to be smooth: the regularised 1/|grad phi|^2 = G/(G^2 + eps^2) is (a hard
+gate at G = eps made the 10000-step map a patchwork of jumps in the far tails).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_adjoint_workload_gradient():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd import pf
+    from paper_2303_09671_amd.adjoint import PartitionCoefficient, Workload, forward_k
+    one_d, two_d, k1t, k2t = I.adjoint_workloads()
+    wls = [Workload(**one_d), Workload(**two_d)]
+    tgts = [torch.tensor(k1t, dtype=torch.float64), torch.tensor([k2t], dtype=torch.float64)]
+    base = one_d["params"]
+    theta0 = np.array([base["A"], base["Mphi"], base["W"]])
+    for wl, kt, name in zip(wls, tgts, ("1D x64", "2D 512^2")):
+        print(f"case: adjoint workload {name}", flush=True)
+        theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+        k = PartitionCoefficient.apply(theta, wl)
+        assert torch.isfinite(k).all()
+        L = ((k - kt) ** 2).sum()
+        L.backward()
+        g = theta.grad.numpy()
+        fds = {}
+        for h in (1e-8, 1e-6):
+            fd = np.zeros(3)
+            for i in range(3):
+                tp, tm = theta0.copy(), theta0.copy()
+                tp[i] += h
+                tm[i] -= h
+                kp, hp, _, _ = forward_k(wl, tp)
+                km, hm, _, _ = forward_k(wl, tm)
+                if True:
+                    assert np.array_equal(pf.pf_solute(hp)[2], pf.pf_solute(hm)[2]), "argmax moved"
+                fd[i] = (((kp - kt) ** 2).sum() - ((km - kt) ** 2).sum()).item() / (2 * h)
+            fds[h] = fd
+        print(f"  grad {g} fd(1e-6) {fds[1e-6]} fd(1e-8) {fds[1e-8]}", flush=True)
+        for h, fd in fds.items():
+            for i in range(3):
+                assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + 1e-9 * np.abs(fd).max(), (name, h, i, g, fd)
