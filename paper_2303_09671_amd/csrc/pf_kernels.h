@@ -61,14 +61,15 @@ struct StreamGeom {
 };
 
 template <int DIM, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __restrict__ iph,
+__global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
                                                     double* __restrict__ oph, double* __restrict__ ocs,
                                                     double* __restrict__ ocl, int zchunk, double t_n,
                                                     double s_n, int do_shift, int* __restrict__ err) {
   using G = StreamGeom<DIM, TX, TY>;
-  __shared__ double su[4][3][G::P2];
+  // ring of three planes (z-1, z, z+1) of (phi, c_s, c_l) with in-plane halo 2
+  __shared__ double su[3][3][G::P2];
   __shared__ double spt[2][G::P1];
   __shared__ double smu[3][G::P1];
   __shared__ double sfx[2][G::NFX];
@@ -84,22 +85,33 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
   const int ox = tid % TX, oy = tid / TX;  // own column
   const int gxo = x0 + ox, gyo = y0 + oy;
   const bool own_valid = (gxo < nx) && (gyo < ny);
+  auto slot3 = [](int gz) { return (gz + 9) % 3; };
 
-  // In-plane global offsets of this thread's ring positions (the same for
-  // every plane): computed once, so a plane load is three loads per position.
+  // In-plane global offsets of this thread's ring positions and cell-stage
+  // positions (the same for every plane), computed once.
   constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
-  long long ld_off[NLD];
+  constexpr int NCS = (G::P1 + G::NT - 1) / G::NT;
+  long long ld_off[NLD], cs_off[NCS];
 #pragma unroll
   for (int r = 0; r < NLD; ++r) {
-    const int i = tid + r * G::NT;
+    const int i = min(tid + r * G::NT, G::P2 - 1);
     const int lx = i % G::BX2 - 2;
     const int ly = i / G::BX2 - G::OY2;
     const int gx = map_axis(x0 + lx, nx, c.px);
     const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
     ld_off[r] = (long long)gx + (long long)nx * gy;
   }
+#pragma unroll
+  for (int r = 0; r < NCS; ++r) {
+    const int i = min(tid + r * G::NT, G::P1 - 1);
+    const int lx = i % G::BX1 - 1;
+    const int ly = i / G::BX1 - G::OY1;
+    const int gx = map_axis(x0 + lx, nx, c.px);
+    const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
+    cs_off[r] = (long long)gx + (long long)nx * gy;
+  }
   auto load_plane = [&](int gz) {
-    const int slot = (gz + 8) & 3;
+    const int slot = slot3(gz);
     const long long zo = plane * mirror_idx(gz, nz);
 #pragma unroll
     for (int r = 0; r < NLD; ++r) {
@@ -113,16 +125,45 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     }
   };
 
-  // phi_t and mu_bar of plane gz on the tile plus in-plane halo 1.
-  auto cell_plane = [&](int gz) {
-    const int s0 = (gz + 8) & 3, sm = (gz + 7) & 3, sp = (gz + 9) & 3;
+  // phi_t and mu_bar of plane gz on the tile plus in-plane halo 1.  Planes gz
+  // and gz-1 are in the ring; the plane above comes from the ring when
+  // up_in_ring, else from global memory (it is loaded into the ring later).
+  // Likewise the plane below comes from global memory when dn_global.
+  auto cell_plane = [&](int gz, bool up_in_ring, bool dn_global) {
+    const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
     const int pt = (gz + 8) & 1, mu = (gz + 9) % 3;
     const double zlab = ((double)gz + s_n + 0.5) * c.dx;
     const double cleq = cleq_at(c, zlab, t_n, c.V, c.z0);
-    for (int i = tid; i < G::P1; i += G::NT) {
+    const long long zup = plane * mirror_idx(gz + 1, nz);
+    const long long zdn = plane * mirror_idx(gz - 1, nz);
+#pragma unroll
+    for (int r = 0; r < NCS; ++r) {
+      const int i = tid + r * G::NT;
+      if (i >= G::P1) continue;
       const int lx = i % G::BX1 - 1;
       const int ly = i / G::BX1 - G::OY1;
       const int ic = G::i2(lx, ly);
+      double upP, upS, upL, dnP, dnS, dnL;
+      if (up_in_ring) {
+        upP = su[sp][0][ic];
+        upS = su[sp][1][ic];
+        upL = su[sp][2][ic];
+      } else {
+        const long long o = cs_off[r] + zup;
+        upP = iph[o];
+        upS = ics[o];
+        upL = icl[o];
+      }
+      if (dn_global) {
+        const long long o = cs_off[r] + zdn;
+        dnP = iph[o];
+        dnS = ics[o];
+        dnL = icl[o];
+      } else {
+        dnP = su[sm][0][ic];
+        dnS = su[sm][1][ic];
+        dnL = su[sm][2][ic];
+      }
       double gph[DIM], gcs[DIM], gcl[DIM];
       const double* U0 = su[s0][0];
       const double* S0 = su[s0][1];
@@ -138,11 +179,10 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
         gcl[1] = (L0[ic + G::BX2] - L0[ic - G::BX2]) * c.inv_2dx;
         lap += (U0[ic + G::BX2] - 2.0 * ph + U0[ic - G::BX2]);
       }
-      const double upz = su[sp][0][ic], umz = su[sm][0][ic];
-      gph[DIM - 1] = (upz - umz) * c.inv_2dx;
-      gcs[DIM - 1] = (su[sp][1][ic] - su[sm][1][ic]) * c.inv_2dx;
-      gcl[DIM - 1] = (su[sp][2][ic] - su[sm][2][ic]) * c.inv_2dx;
-      lap += (upz - 2.0 * ph + umz);
+      gph[DIM - 1] = (upP - dnP) * c.inv_2dx;
+      gcs[DIM - 1] = (upS - dnS) * c.inv_2dx;
+      gcl[DIM - 1] = (upL - dnL) * c.inv_2dx;
+      lap += (upP - 2.0 * ph + dnP);
       lap *= c.inv_dx2;
       double phit, mubar;
       cell_stage<DIM>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
@@ -158,7 +198,7 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
       Fl = 0.0;
       return;
     }
-    const int sa = (gz + 8) & 3, sb = (gz + 9) & 3;
+    const int sa = slot3(gz), sb = slot3(gz + 1);
     const int pa = (gz + 8) & 1, pb = (gz + 9) & 1;
     const int ma = (gz + 9) % 3, mb = (gz + 10) % 3;
     const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
@@ -186,7 +226,7 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
     face_flux<DIM, DIM - 1>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
-                   Fl);
+                            Fl);
   };
 
   // Faces normal to in-plane axis K (0 = x, 1 = y) of plane gz into LDS.
@@ -194,7 +234,7 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     constexpr int K = decltype(axis)::value;
     constexpr int NF = (K == 0) ? G::NFX : G::NFY;
     constexpr int RW = (K == 0) ? TX + 1 : TX;  // faces per row
-    const int s0 = (gz + 8) & 3, sm = (gz + 7) & 3, sp = (gz + 9) & 3;
+    const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
     const int pt = (gz + 8) & 1;
     const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
     double* F0 = (K == 0) ? sfx[0] : sfy[0];
@@ -203,7 +243,7 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
       const int fa = f % RW, fb = f / RW;
       // cell a = (ax, ay), cell b = a + e_K
       const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
-      const int bx = (K == 0) ? fa : fa, by = (K == 0) ? fb : fb;
+      const int bx = fa, by = fb;
       const int gface = (K == 0) ? x0 + fa : y0 + fb;
       const int nk = (K == 0) ? nx : ny;
       const int pk = (K == 0) ? c.px : c.py;
@@ -244,20 +284,18 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     }
   };
 
-  // ---- prologue
-  for (int g = zb - 2; g <= zb + 1; ++g) load_plane(g);
+  // ---- prologue: ring = planes zb-1, zb, zb+1; rates of planes zb-1 and zb
+  for (int g = zb - 1; g <= zb + 1; ++g) load_plane(g);
   __syncthreads();
-  cell_plane(zb - 1);
-  cell_plane(zb);
+  cell_plane(zb - 1, true, true);
+  cell_plane(zb, true, false);
   __syncthreads();
   double FsD, FlD;  // flux through the face below the current plane
   zface(zb - 1, FsD, FlD);
 
   int errbits = 0;
   for (int z = zb; z < ze; ++z) {
-    load_plane(z + 2);
-    __syncthreads();
-    cell_plane(z + 1);
+    cell_plane(z + 1, false, false);  // plane z+2 read from global memory
     __syncthreads();
     inplane_faces(std::integral_constant<int, 0>{}, z);
     if constexpr (DIM == 3) inplane_faces(std::integral_constant<int, 1>{}, z);
@@ -265,7 +303,7 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     zface(z, FsU, FlU);
     __syncthreads();
     if (own_valid) {
-      const int s0 = (z + 8) & 3;
+      const int s0 = slot3(z);
       const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
       const double ph = su[s0][0][ic], cs = su[s0][1][ic], cl = su[s0][2][ic];
       const double pt = spt[(z + 8) & 1][i1];
@@ -307,6 +345,8 @@ __global__ __launch_bounds__(TX * TY) void k_stream(Const c, const double* __res
     }
     FsD = FsU;
     FlD = FlU;
+    load_plane(z + 2);  // into the slot of plane z-1 (no longer read)
+    __syncthreads();
   }
   if (errbits) atomicOr(err, errbits);
 }
