@@ -24,6 +24,8 @@ struct Const {
   double dx, inv_dx, inv_2dx, inv_4dx, inv_dx2, dt;
   double W, W2, alpha, lambda, lambda0, Mphi;
   double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad, eps2;
+  double eps2s, onemA_dx2;  // eps^2 dx^4 and (1-A) dx^2 of the dx-scaled face stage
+  double inv_ke;
 };
 
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
@@ -84,6 +86,12 @@ __device__ __forceinline__ void interp(const Const& c, double phi, double& p, do
     hq = om * om * (3.0 - 2.0 * om);
     dh = 6.0 * w;
   }
+  if (c.ap == 0.0) {  // uniform branch: the common case p = h
+    p = h;
+    q = hq;
+    dp = dh;
+    return;
+  }
   const double a = c.ap * (phi - 0.5) * w * w;
   p = h + a;
   q = hq - a;
@@ -93,7 +101,6 @@ __device__ __forceinline__ void interp(const Const& c, double phi, double& p, do
 
 __device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p, double& q) {
   const double om = 1.0 - phi;
-  const double w = phi * om;
   double h, hq;
   if (c.quintic) {
     h = phi * phi * phi * (phi * (6.0 * phi - 15.0) + 10.0);
@@ -102,6 +109,12 @@ __device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p,
     h = phi * phi * (3.0 - 2.0 * phi);
     hq = om * om * (3.0 - 2.0 * om);
   }
+  if (c.ap == 0.0) {
+    p = h;
+    q = hq;
+    return;
+  }
+  const double w = phi * om;
   const double a = c.ap * (phi - 0.5) * w * w;
   p = h + a;
   q = hq - a;
@@ -110,7 +123,7 @@ __device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p,
 // Equilibrium liquid concentration of the frozen temperature field at lab
 // height zlab and time t (Eqs. dil7, ds1, reference (c_inf, T_s) at z0).
 __device__ __forceinline__ double cleq_at(const Const& c, double zlab, double t, double V, double z0) {
-  return (1.0 - (1.0 - c.ke) * (zlab - z0 - V * t) * c.inv_lT) / c.ke;
+  return (1.0 - (1.0 - c.ke) * (zlab - z0 - V * t) * c.inv_lT) * c.inv_ke;
 }
 
 // mu_bar = p mu_s + (1-p) mu_l (units of Omega, up to a constant) of one cell.
@@ -166,36 +179,43 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
-// through a face normal to axis K.  phf, csf, clf, ptf are the face means;
-// g*[j] the face gradient (compact along K, mean of central differences
-// across K) of phi, mu_bar, c_s, c_l.  With gam = G/(G^2 + eps^2) (regularised
-// 1/|grad phi|^2) and R = (grad phi)_K gam / Mbar:
+// through a face normal to axis K, in dx-scaled form.  phf, csf, clf, ptf are
+// the face means; g*[K] is the plain difference u_b - u_a across the face and
+// g*[j], j != K, the sum of the central differences (u_{+j} - u_{-j}) of the two
+// cells beside it, so the face gradient is (g[K], g[j]/4) / dx.  With
+// gam = G/(G^2 + eps^2) (regularised 1/|grad phi|^2) and R = (grad phi)_K gam / Mbar:
 //   q_n (n n^T grad mu_bar)_K = M_s M_l (b p + 1 - p) (grad phi . grad mu_bar) R,
 //   ((1 - n n^T) grad c)_K    = (grad c)_K - (grad phi . grad c) Mbar R,
 //   anti-trapping_s / _l      = +/- (1-A)(c_s - c_l) phi_t R M_s(1-p) / b M_l p.
+// Returned: dx times the fluxes (divergence = sum of differences / dx^2).  In
+// scaled units G' = dx^2 G, eps'^2 = dx^4 eps^2 and R' = R / dx, which leaves
+// every term but the anti-trapping one (factor dx^2) unchanged in form.
 template <int DIM, int K>
 __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf, double clf, double ptf,
                                           const double* gph, const double* gmu, const double* gcs,
                                           const double* gcl, double& Fs, double& Fl) {
   double p, q;
   interp_pq(c, phf, p, q);
-  double G = 0.0, dmu = 0.0, dcs = 0.0, dcl = 0.0;
+  double G = gph[K] * gph[K], dmu = gph[K] * gmu[K], dcs = gph[K] * gcs[K], dcl = gph[K] * gcl[K];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    G += gph[j] * gph[j];
-    dmu += gph[j] * gmu[j];
-    dcs += gph[j] * gcs[j];
-    dcl += gph[j] * gcl[j];
+    if (j == K) continue;
+    const double t = 0.0625 * gph[j];
+    G = __builtin_fma(t, gph[j], G);
+    dmu = __builtin_fma(t, gmu[j], dmu);
+    dcs = __builtin_fma(t, gcs[j], dcs);
+    dcl = __builtin_fma(t, gcl[j], dcl);
   }
   const double Ms = c.Ds * csf;
   const double Ml = clf;
   const double ms = Ms * q, ml = c.b * Ml * p;
   const double Mb = ms + ml;
-  const double R = gph[K] * G * frcp(Mb * (G * G + c.eps2));
+  const double R = gph[K] * G * frcp(Mb * (G * G + c.eps2s));
   const double nrm = Ms * Ml * (c.b * p + q) * dmu * R;
-  const double at = c.onemA * (csf - clf) * ptf * R;
-  Fs = nrm + c.Ds * (gcs[K] - dcs * Mb * R) + at * ms;
-  Fl = nrm + (gcl[K] - dcl * Mb * R) - at * ml;
+  const double at = c.onemA_dx2 * (csf - clf) * ptf * R;
+  const double MbR = Mb * R;
+  Fs = nrm + c.Ds * (gcs[K] - dcs * MbR) + at * ms;
+  Fl = nrm + (gcl[K] - dcl * MbR) - at * ml;
 }
 
 // Error word bits.

@@ -207,22 +207,22 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
     const double ca = su[sa][1][ic], cb = su[sb][1][ic];
     const double la = su[sa][2][ic], lb = su[sb][2][ic];
     const int k = DIM - 1;
-    gph[k] = (pb_ - pa_) * c.inv_dx;
-    gmu[k] = (smu[mb][i1] - smu[ma][i1]) * c.inv_dx;
-    gcs[k] = (cb - ca) * c.inv_dx;
-    gcl[k] = (lb - la) * c.inv_dx;
+    gph[k] = pb_ - pa_;  // dx-scaled face stage: plain differences and sums of them
+    gmu[k] = smu[mb][i1] - smu[ma][i1];
+    gcs[k] = cb - ca;
+    gcl[k] = lb - la;
     {  // x
-      gph[0] = ((su[sa][0][ic + 1] - su[sa][0][ic - 1]) + (su[sb][0][ic + 1] - su[sb][0][ic - 1])) * c.inv_4dx;
-      gmu[0] = ((smu[ma][i1 + 1] - smu[ma][i1 - 1]) + (smu[mb][i1 + 1] - smu[mb][i1 - 1])) * c.inv_4dx;
-      gcs[0] = ((su[sa][1][ic + 1] - su[sa][1][ic - 1]) + (su[sb][1][ic + 1] - su[sb][1][ic - 1])) * c.inv_4dx;
-      gcl[0] = ((su[sa][2][ic + 1] - su[sa][2][ic - 1]) + (su[sb][2][ic + 1] - su[sb][2][ic - 1])) * c.inv_4dx;
+      gph[0] = (su[sa][0][ic + 1] - su[sa][0][ic - 1]) + (su[sb][0][ic + 1] - su[sb][0][ic - 1]);
+      gmu[0] = (smu[ma][i1 + 1] - smu[ma][i1 - 1]) + (smu[mb][i1 + 1] - smu[mb][i1 - 1]);
+      gcs[0] = (su[sa][1][ic + 1] - su[sa][1][ic - 1]) + (su[sb][1][ic + 1] - su[sb][1][ic - 1]);
+      gcl[0] = (su[sa][2][ic + 1] - su[sa][2][ic - 1]) + (su[sb][2][ic + 1] - su[sb][2][ic - 1]);
     }
     if (DIM == 3) {
       const int d2 = G::BX2, d1 = G::BX1;
-      gph[1] = ((su[sa][0][ic + d2] - su[sa][0][ic - d2]) + (su[sb][0][ic + d2] - su[sb][0][ic - d2])) * c.inv_4dx;
-      gmu[1] = ((smu[ma][i1 + d1] - smu[ma][i1 - d1]) + (smu[mb][i1 + d1] - smu[mb][i1 - d1])) * c.inv_4dx;
-      gcs[1] = ((su[sa][1][ic + d2] - su[sa][1][ic - d2]) + (su[sb][1][ic + d2] - su[sb][1][ic - d2])) * c.inv_4dx;
-      gcl[1] = ((su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2])) * c.inv_4dx;
+      gph[1] = (su[sa][0][ic + d2] - su[sa][0][ic - d2]) + (su[sb][0][ic + d2] - su[sb][0][ic - d2]);
+      gmu[1] = (smu[ma][i1 + d1] - smu[ma][i1 - d1]) + (smu[mb][i1 + d1] - smu[mb][i1 - d1]);
+      gcs[1] = (su[sa][1][ic + d2] - su[sa][1][ic - d2]) + (su[sb][1][ic + d2] - su[sb][1][ic - d2]);
+      gcl[1] = (su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2]);
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
     face_flux<DIM, DIM - 1>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
@@ -239,7 +239,18 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
     const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
     double* F0 = (K == 0) ? sfx[0] : sfy[0];
     double* F1 = (K == 0) ? sfx[1] : sfy[1];
-    for (int f = tid; f < NF; f += G::NT) {
+    // One face per thread, and the NF - NT faces left over go to one wave
+    // chosen per axis (x: wave 2, y: wave 3; the extra cells of the cell stage
+    // fall on waves 0 and 1), so the four waves carry equal work per plane.
+    constexpr int NW = G::NT / 64;
+    constexpr int E = NF - G::NT;
+    static_assert(E >= 0 && E <= 64, "tile shape: leftover faces must fit one wave");
+    constexpr int WE = (K + 2 < NW) ? K + 2 : NW - 1;
+    const int le = tid - 64 * WE;
+    const bool extra = (E > 0) && le >= 0 && le < E;
+    for (int it = 0; it < 2; ++it) {
+      if (it == 1 && !extra) break;
+      const int f = (it == 0) ? tid : G::NT + le;
       const int fa = f % RW, fb = f / RW;
       // cell a = (ax, ay), cell b = a + e_K
       const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
@@ -258,24 +269,24 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       const double pa = su[s0][0][ia], pb = su[s0][0][ib];
       const double ca = su[s0][1][ia], cb = su[s0][1][ib];
       const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
-      gph[K] = (pb - pa) * c.inv_dx;
-      gmu[K] = (smu[m0][jb] - smu[m0][ja]) * c.inv_dx;
-      gcs[K] = (cb - ca) * c.inv_dx;
-      gcl[K] = (lb_ - la_) * c.inv_dx;
+      gph[K] = pb - pa;  // dx-scaled face stage: plain differences and sums of them
+      gmu[K] = smu[m0][jb] - smu[m0][ja];
+      gcs[K] = cb - ca;
+      gcl[K] = lb_ - la_;
       if (DIM == 3) {  // the other in-plane axis
         constexpr int J = 1 - K;
         constexpr int d2 = (J == 0) ? 1 : G::BX2;
         constexpr int d1 = (J == 0) ? 1 : G::BX1;
-        gph[J] = ((su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2])) * c.inv_4dx;
-        gmu[J] = ((smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1])) * c.inv_4dx;
-        gcs[J] = ((su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2])) * c.inv_4dx;
-        gcl[J] = ((su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2])) * c.inv_4dx;
+        gph[J] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
+        gmu[J] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
+        gcs[J] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
+        gcl[J] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
       }
       constexpr int kz = DIM - 1;  // transverse z
-      gph[kz] = ((su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib])) * c.inv_4dx;
-      gmu[kz] = ((smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb])) * c.inv_4dx;
-      gcs[kz] = ((su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib])) * c.inv_4dx;
-      gcl[kz] = ((su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib])) * c.inv_4dx;
+      gph[kz] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
+      gmu[kz] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
+      gcs[kz] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
+      gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
       const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
       double Fs, Fl;
       face_flux<DIM, K>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
@@ -318,8 +329,8 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       double p, q, dp;
       interp(c, ph, p, q, dp);
       const double src = -c.A * (cs - cl) * dp * pt;
-      const double ncs = cs + c.dt * (divs * c.inv_dx + src);
-      const double ncl = cl + c.dt * (divl * c.inv_dx + src);
+      const double ncs = cs + c.dt * (divs * c.inv_dx2 + src);
+      const double ncl = cl + c.dt * (divl * c.inv_dx2 + src);
       const double nph = ph + c.dt * pt;
       errbits |= check_bits(nph, ncs, ncl);
       const long long col = (long long)gxo + (long long)nx * gyo;
@@ -514,10 +525,10 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
           mb = MU[k];
         }
       }
-      double g0[1] = {(pb - pa) * c.inv_dx};
-      double g1[1] = {(mb - ma) * c.inv_dx};
-      double g2[1] = {(sb - sa) * c.inv_dx};
-      double g3[1] = {(lb - la) * c.inv_dx};
+      double g0[1] = {pb - pa};  // dx-scaled face stage: plain differences
+      double g1[1] = {mb - ma};
+      double g2[1] = {sb - sa};
+      double g3[1] = {lb - la};
       face_flux<1, 0>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3, Fs, Fl);
     };
     double FsL, FlL;
@@ -530,8 +541,8 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
         double p, q, dp;
         interp(c, P[k], p, q, dp);
         const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
-        const double ns = S[k] + dt * ((FsR - FsL) * c.inv_dx + src);
-        const double nl = L[k] + dt * ((FlR - FlL) * c.inv_dx + src);
+        const double ns = S[k] + dt * ((FsR - FsL) * c.inv_dx2 + src);
+        const double nl = L[k] + dt * ((FlR - FlL) * c.inv_dx2 + src);
         P[k] = P[k] + dt * PT[k];
         S[k] = ns;
         L[k] = nl;

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -34,9 +35,17 @@ int fail(int code, const std::string& msg) {
       return fail(PF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
   } while (0)
 
-// Launch geometry of the streaming kernel.
-constexpr int S3_TX = 32, S3_TY = 8, S3_ZC = 32;  // 3D: 256 threads, 32-plane chunks
-constexpr int S2_TX = 64, S2_ZC = 16;             // 2D: 64 threads, 16-plane chunks
+// Launch geometry of the streaming kernel: in-plane tiles; the z range of a
+// grid column is cut into chunks so that the launch holds about `target`
+// workgroups (prologue cost: two extra planes of cell rates per chunk).
+constexpr int S3_TX = 32, S3_TY = 8;  // 3D: 256 threads (4 waves), 3 workgroups per CU
+constexpr int S2_TX = 64;             // 2D: 64 threads (1 wave)
+
+int zchunk_for(int nz, long long tiles, long long target, int zmin) {
+  long long split = std::max<long long>(1, (target + tiles - 1) / tiles);
+  int zc = (int)((nz + split - 1) / split);
+  return std::max(std::min(zc, nz), std::min(zmin, nz));
+}
 
 }  // namespace
 
@@ -69,6 +78,7 @@ struct pf_handle {
   pfadj::Tile1* d_tiles = nullptr;   // adjoint: (run, tile) table of 1D runs
   int ntiles = 0;
   int* d_err = nullptr;
+  int zchunk = 32;  // z planes per workgroup of the streaming kernel
   long long n = 0;  // step counter
 
   pfk::RunTab runtab() const {
@@ -196,6 +206,9 @@ pfk::Const make_const(const pf_params& p) {
   c.z0 = p.z0;
   c.eps_grad = p.eps_grad;
   c.eps2 = p.eps_grad * p.eps_grad;
+  c.eps2s = c.eps2 * (p.dx * p.dx) * (p.dx * p.dx);
+  c.onemA_dx2 = (1.0 - p.A) * p.dx * p.dx;
+  c.inv_ke = 1.0 / p.ke;
   return c;
 }
 
@@ -220,13 +233,15 @@ int launch_stream(pf_handle* h, double* const src[3], double* const dst[3], long
   const double sn = std::floor(c.V * tn / c.dx);
   const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > sn) ? 1 : 0;
   if (c.dim == 3) {
-    dim3 grid((c.nx + S3_TX - 1) / S3_TX, (c.ny + S3_TY - 1) / S3_TY, (c.nz + S3_ZC - 1) / S3_ZC);
+    const int zc = h->zchunk;
+    dim3 grid((c.nx + S3_TX - 1) / S3_TX, (c.ny + S3_TY - 1) / S3_TY, (c.nz + zc - 1) / zc);
     hipLaunchKernelGGL((pfk::k_stream<3, S3_TX, S3_TY>), grid, dim3(S3_TX * S3_TY), 0, h->stream, c, src[0],
-                       src[1], src[2], dst[0], dst[1], dst[2], S3_ZC, tn, sn, sh, h->d_err);
+                       src[1], src[2], dst[0], dst[1], dst[2], zc, tn, sn, sh, h->d_err);
   } else {
-    dim3 grid((c.nx + S2_TX - 1) / S2_TX, 1, (c.nz + S2_ZC - 1) / S2_ZC);
+    const int zc = h->zchunk;
+    dim3 grid((c.nx + S2_TX - 1) / S2_TX, 1, (c.nz + zc - 1) / zc);
     hipLaunchKernelGGL((pfk::k_stream<2, S2_TX, 1>), grid, dim3(S2_TX), 0, h->stream, c, src[0], src[1], src[2],
-                       dst[0], dst[1], dst[2], S2_ZC, tn, sn, sh, h->d_err);
+                       dst[0], dst[1], dst[2], zc, tn, sn, sh, h->d_err);
   }
   PF_HIP(hipGetLastError());
   return PF_OK;
@@ -366,6 +381,20 @@ int pf_create(const pf_params* p, double* phi, double* cs, double* cl, void* str
   if (!h->batched) {
     for (int k = 0; k < 3; ++k)
       if ((rc = dalloc(&h->tw[k], (size_t)h->ntot))) return cleanup_fail(rc);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const pfk::Const& c = h->c;
+    if (c.dim == 3) {
+      const long long tiles = (long long)((c.nx + S3_TX - 1) / S3_TX) * ((c.ny + S3_TY - 1) / S3_TY);
+      h->zchunk = zchunk_for(c.nz, tiles, 11LL * ncu, 16);  // ~3.7 rounds of 3 workgroups per CU
+    } else {
+      const long long tiles = (c.nx + S2_TX - 1) / S2_TX;
+      h->zchunk = zchunk_for(c.nz, tiles, 16LL * ncu, 8);  // 4 one-wave workgroups per SIMD
+    }
+    if (const char* e = std::getenv("PF_ZCHUNK")) {  // tuning override
+      const int v = std::atoi(e);
+      if (v > 0) h->zchunk = v;
+    }
   }
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return cleanup_fail(fail(PF_EDEVICE, hipGetErrorString(e)));

@@ -5,9 +5,14 @@ dL/dtheta, theta = (A, M_phi, W), from the adjoint must agree with central
 finite differences to 1e-5 relative; the argmax cell of every run must not move
 between the +h and -h runs (max() is differentiated through it).
 
-Checked at h = 1e-6 (the configured step) and h = 1e-8.  Both need the step
-map to be smooth: the regularised 1/|grad phi|^2 = G/(G^2 + eps^2) is (a hard
-gate at G = eps made the 10000-step map a patchwork of jumps in the far tails).
+Checked at h = 1e-6 (the configured step; bar 1e-5 relative per component)
+and, as a cross-check that the agreement is not an artefact of the FD
+truncation error, at h = 1e-8.  At h = 1e-8 the quotient carries the rounding
+noise of the 10000-step forward, delta L / (2 h) with delta L ~ 1e-14 (a few
+1e-7 absolute), so there the floor is 1e-5 of the largest component rather than
+of each one.  Both need the step map to be smooth: the regularised
+1/|grad phi|^2 = G/(G^2 + eps^2) is (a hard gate at G = eps made the
+10000-step map a patchwork of jumps in the far tails).
 """
 import numpy as np
 import pytest
@@ -50,5 +55,6 @@ def test_adjoint_workload_gradient():
             fds[h] = fd
         print(f"  grad {g} fd(1e-6) {fds[1e-6]} fd(1e-8) {fds[1e-8]}", flush=True)
         for h, fd in fds.items():
+            floor = 1e-9 if h == 1e-6 else 1e-5  # relative to max |fd|: FD rounding noise at h = 1e-8
             for i in range(3):
-                assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + 1e-9 * np.abs(fd).max(), (name, h, i, g, fd)
+                assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + floor * np.abs(fd).max(), (name, h, i, g, fd)
