@@ -26,6 +26,7 @@ struct Const {
   double Ds, ke, log_ke, A, onemA, b, ap, inv_lT, V, z0, eps_grad, eps2;
   double eps2s, onemA_dx2;  // eps^2 dx^4 and (1-A) dx^2 of the dx-scaled face stage
   double inv_ke;
+  double W2_dx2, eps2r, onemA_4dx2;  // W^2/dx^2, 16 eps^2 dx^4, 4 (1-A) dx^2: plain-difference cell stage
 };
 
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
@@ -73,6 +74,9 @@ __device__ __forceinline__ double flog(double x) {
 // Interpolation p(phi) = h + a_p (phi - 1/2) phi^2 (1-phi)^2 (Eq. interpolation2),
 // its complement q = 1 - p evaluated as p(1 - phi) (antisymmetry of p; avoids the
 // cancellation of 1 - p near phi = 1), and p'(phi).
+// APZ: a_p is known to be zero at compile time (p = h); the launch picks the
+// instantiation from the handle's a_p.
+template <bool APZ = false>
 __device__ __forceinline__ void interp(const Const& c, double phi, double& p, double& q, double& dp) {
   const double om = 1.0 - phi;
   const double w = phi * om;
@@ -86,19 +90,20 @@ __device__ __forceinline__ void interp(const Const& c, double phi, double& p, do
     hq = om * om * (3.0 - 2.0 * om);
     dh = 6.0 * w;
   }
-  if (c.ap == 0.0) {  // uniform branch: the common case p = h
+  if constexpr (APZ) {
     p = h;
     q = hq;
     dp = dh;
-    return;
+  } else {
+    const double a = c.ap * (phi - 0.5) * w * w;
+    p = h + a;
+    q = hq - a;
+    const double tt = 1.0 - 2.0 * phi;
+    dp = dh + c.ap * w * (w - tt * tt);
   }
-  const double a = c.ap * (phi - 0.5) * w * w;
-  p = h + a;
-  q = hq - a;
-  const double tt = 1.0 - 2.0 * phi;
-  dp = dh + c.ap * w * (w - tt * tt);
 }
 
+template <bool APZ = false>
 __device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p, double& q) {
   const double om = 1.0 - phi;
   double h, hq;
@@ -109,15 +114,15 @@ __device__ __forceinline__ void interp_pq(const Const& c, double phi, double& p,
     h = phi * phi * (3.0 - 2.0 * phi);
     hq = om * om * (3.0 - 2.0 * om);
   }
-  if (c.ap == 0.0) {
+  if constexpr (APZ) {
     p = h;
     q = hq;
-    return;
+  } else {
+    const double w = phi * om;
+    const double a = c.ap * (phi - 0.5) * w * w;
+    p = h + a;
+    q = hq - a;
   }
-  const double w = phi * om;
-  const double a = c.ap * (phi - 0.5) * w * w;
-  p = h + a;
-  q = hq - a;
 }
 
 // Equilibrium liquid concentration of the frozen temperature field at lab
@@ -135,8 +140,6 @@ __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs
 }
 
 // Cell stage: phi_t (Eq. phasefield_nonvar divided by H) and mu_bar.
-//   g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
-//   compact Laplacian of phi.
 // With Mbar = M_s(1-p) + b M_l p, G = |grad phi|^2, the regularised inverse
 // gam = G / S, S = G^2 + eps^2, and the drag numerator
 // Dn = M_s(1-p)(1 - A(1-p)) + A b M_l p^2 (drag D = Dn / Mbar), the rate
@@ -144,13 +147,16 @@ __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs
 //   X   = lambda (1-A) dc p(1-p) (Ds grad c_s - b grad c_l).grad phi gam / Mbar,
 //   tau = alpha + lambda (1-A)^2 dc^2 b p(1-p) gam / (Mbar (b p + 1 - p)),
 // is evaluated with numerator and prefactor multiplied by Q = Mbar (b p + 1 - p) S:
-// one reciprocal.
-template <int DIM>
-__device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
-                                           const double* gph, const double* gcs, const double* gcl,
-                                           double lap, double& phit, double& mubar) {
+// one reciprocal.  cell_core takes G and dot = (Ds grad c_s - b grad c_l).grad phi
+// in units where the true values are k G and k dot, with eps2x = eps^2 / k^2 and
+// onemAx = (1 - A) / k (the common factor k^2 of numerator and prefactor cancels);
+// Wlap is W^2 lap.
+template <bool APZ>
+__device__ __forceinline__ void cell_core(const Const& c, double cleq, double phi, double cs, double cl, double G,
+                                          double dot, double Wlap, double eps2x, double onemAx, double& phit,
+                                          double& mubar) {
   double p, q, dp;
-  interp(c, phi, p, q, dp);
+  interp<APZ>(c, phi, p, q, dp);
   const double ll = flog(cl);
   const double dmu = flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
   mubar = ll + p * dmu;
@@ -160,22 +166,46 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
   const double ml = c.b * cl * p;                           // b M_l p
   const double Mb = ms + ml;
   const double Dn = ms * (1.0 - c.A * q) + c.A * ml * p;
+  const double S = G * G + eps2x;
+  const double bq = c.b * p + q;
+  const double Q = Mb * bq * S;
+  const double pq = p * q;
+  const double lAdc = c.lambda * c.onemA * dc;
+  const double fdw = 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
+  const double base = Wlap - fdw - c.lambda * dGc * dp;
+  const double num = base * Q + c.lambda * Dn * dc * dmu * dp * bq * S + lAdc * pq * dot * G * bq;
+  const double den = c.alpha * Q + lAdc * onemAx * dc * c.b * pq * G;
+  phit = num * frcp(den);
+}
+
+// g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
+// compact Laplacian of phi.
+template <int DIM, bool APZ = false>
+__device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
+                                           const double* gph, const double* gcs, const double* gcl,
+                                           double lap, double& phit, double& mubar) {
   double G = 0.0, dot = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     G += gph[k] * gph[k];
     dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
   }
-  const double S = G * G + c.eps2;
-  const double bq = c.b * p + q;
-  const double Q = Mb * bq * S;
-  const double pq = p * q;
-  const double lAdc = c.lambda * c.onemA * dc;
-  const double fdw = 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
-  const double base = c.W2 * lap - fdw - c.lambda * dGc * dp;
-  const double num = base * Q + c.lambda * Dn * dc * dmu * dp * bq * S + lAdc * pq * dot * G * bq;
-  const double den = c.alpha * Q + lAdc * c.onemA * dc * c.b * pq * G;
-  phit = num * frcp(den);
+  cell_core<APZ>(c, cleq, phi, cs, cl, G, dot, c.W2 * lap, c.eps2, c.onemA, phit, mubar);
+}
+
+// The same from plain differences: d*[k] = u_{+k} - u_{-k} and lsum the sum over
+// axes of u_{+k} - 2 u + u_{-k} (k = 1 / (4 dx^2)).
+template <int DIM, bool APZ = false>
+__device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, double phi, double cs, double cl,
+                                               const double* dph, const double* dcs, const double* dcl,
+                                               double lsum, double& phit, double& mubar) {
+  double G = 0.0, dot = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    G += dph[k] * dph[k];
+    dot += (c.Ds * dcs[k] - c.b * dcl[k]) * dph[k];
+  }
+  cell_core<APZ>(c, cleq, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
@@ -190,12 +220,12 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
 // Returned: dx times the fluxes (divergence = sum of differences / dx^2).  In
 // scaled units G' = dx^2 G, eps'^2 = dx^4 eps^2 and R' = R / dx, which leaves
 // every term but the anti-trapping one (factor dx^2) unchanged in form.
-template <int DIM, int K>
+template <int DIM, int K, bool APZ = false>
 __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf, double clf, double ptf,
                                           const double* gph, const double* gmu, const double* gcs,
                                           const double* gcl, double& Fs, double& Fl) {
   double p, q;
-  interp_pq(c, phf, p, q);
+  interp_pq<APZ>(c, phf, p, q);
   double G = gph[K] * gph[K], dmu = gph[K] * gmu[K], dcs = gph[K] * gcs[K], dcl = gph[K] * gcl[K];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {

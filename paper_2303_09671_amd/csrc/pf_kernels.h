@@ -60,7 +60,7 @@ struct StreamGeom {
   __device__ static __forceinline__ int i1(int lx, int ly) { return (lx + 1) + BX1 * (ly + OY1); }
 };
 
-template <int DIM, int TX, int TY>
+template <int DIM, int TX, int TY, bool APZ>
 __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
@@ -87,11 +87,37 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   const bool own_valid = (gxo < nx) && (gyo < ny);
   auto slot3 = [](int gz) { return (gz + 9) % 3; };
 
+  // Cell-stage positions of this thread on the tile plus in-plane halo 1:
+  // item 0 is the own column (so a 16-lane group reads one LDS row, free of
+  // bank conflicts), item 1 one of the NP1 - NT halo cells (the rows below and
+  // above the tile, then the columns left and right), taken by the first
+  // threads.
+  constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
+  constexpr int NCS = 2;
+  constexpr int NHALO = G::P1 - G::NT;
+  static_assert(NHALO > 0 && NHALO <= G::NT, "tile shape: halo cells must fit one item per thread");
+  auto cs_pos = [&](int r, int& lx, int& ly) {
+    if (r == 0) {
+      lx = ox;
+      ly = oy;
+      return true;
+    }
+    constexpr int NROW = (DIM == 3) ? 2 * G::BX1 : 0;
+    const int h = min(tid, NHALO - 1);
+    if (h < NROW) {
+      ly = (h < G::BX1) ? -1 : TY;
+      lx = h % G::BX1 - 1;
+    } else {
+      const int k = h - NROW;
+      lx = (k & 1) ? TX : -1;
+      ly = k >> 1;
+    }
+    return tid < NHALO;
+  };
+
   // In-plane global offsets of this thread's ring positions and cell-stage
   // positions (the same for every plane), computed once.
-  constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
-  constexpr int NCS = (G::P1 + G::NT - 1) / G::NT;
-  long long ld_off[NLD], cs_off[NCS];
+  int ld_off[NLD], cs_off[NCS];  // x + nx y (a plane holds fewer than 2^31 cells)
 #pragma unroll
   for (int r = 0; r < NLD; ++r) {
     const int i = min(tid + r * G::NT, G::P2 - 1);
@@ -99,16 +125,15 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
     const int ly = i / G::BX2 - G::OY2;
     const int gx = map_axis(x0 + lx, nx, c.px);
     const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
-    ld_off[r] = (long long)gx + (long long)nx * gy;
+    ld_off[r] = gx + nx * gy;
   }
 #pragma unroll
   for (int r = 0; r < NCS; ++r) {
-    const int i = min(tid + r * G::NT, G::P1 - 1);
-    const int lx = i % G::BX1 - 1;
-    const int ly = i / G::BX1 - G::OY1;
+    int lx, ly;
+    cs_pos(r, lx, ly);
     const int gx = map_axis(x0 + lx, nx, c.px);
     const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
-    cs_off[r] = (long long)gx + (long long)nx * gy;
+    cs_off[r] = gx + nx * gy;
   }
   auto load_plane = [&](int gz) {
     const int slot = slot3(gz);
@@ -138,10 +163,9 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
     const long long zdn = plane * mirror_idx(gz - 1, nz);
 #pragma unroll
     for (int r = 0; r < NCS; ++r) {
-      const int i = tid + r * G::NT;
-      if (i >= G::P1) continue;
-      const int lx = i % G::BX1 - 1;
-      const int ly = i / G::BX1 - G::OY1;
+      int lx, ly;
+      if (!cs_pos(r, lx, ly)) continue;
+      const int i = G::i1(lx, ly);
       const int ic = G::i2(lx, ly);
       double upP, upS, upL, dnP, dnS, dnL;
       if (up_in_ring) {
@@ -169,23 +193,22 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       const double* S0 = su[s0][1];
       const double* L0 = su[s0][2];
       const double ph = U0[ic], cs = S0[ic], cl = L0[ic];
-      gph[0] = (U0[ic + 1] - U0[ic - 1]) * c.inv_2dx;
-      gcs[0] = (S0[ic + 1] - S0[ic - 1]) * c.inv_2dx;
-      gcl[0] = (L0[ic + 1] - L0[ic - 1]) * c.inv_2dx;
+      gph[0] = U0[ic + 1] - U0[ic - 1];  // plain differences (cell_stage_raw)
+      gcs[0] = S0[ic + 1] - S0[ic - 1];
+      gcl[0] = L0[ic + 1] - L0[ic - 1];
       double lap = (U0[ic + 1] - 2.0 * ph + U0[ic - 1]);
       if (DIM == 3) {
-        gph[1] = (U0[ic + G::BX2] - U0[ic - G::BX2]) * c.inv_2dx;
-        gcs[1] = (S0[ic + G::BX2] - S0[ic - G::BX2]) * c.inv_2dx;
-        gcl[1] = (L0[ic + G::BX2] - L0[ic - G::BX2]) * c.inv_2dx;
+        gph[1] = U0[ic + G::BX2] - U0[ic - G::BX2];
+        gcs[1] = S0[ic + G::BX2] - S0[ic - G::BX2];
+        gcl[1] = L0[ic + G::BX2] - L0[ic - G::BX2];
         lap += (U0[ic + G::BX2] - 2.0 * ph + U0[ic - G::BX2]);
       }
-      gph[DIM - 1] = (upP - dnP) * c.inv_2dx;
-      gcs[DIM - 1] = (upS - dnS) * c.inv_2dx;
-      gcl[DIM - 1] = (upL - dnL) * c.inv_2dx;
+      gph[DIM - 1] = upP - dnP;
+      gcs[DIM - 1] = upS - dnS;
+      gcl[DIM - 1] = upL - dnL;
       lap += (upP - 2.0 * ph + dnP);
-      lap *= c.inv_dx2;
       double phit, mubar;
-      cell_stage<DIM>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
+      cell_stage_raw<DIM, APZ>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
       spt[pt][i] = phit;
       smu[mu][i] = mubar;
     }
@@ -225,7 +248,7 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       gcl[1] = (su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2]);
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
-    face_flux<DIM, DIM - 1>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
+    face_flux<DIM, DIM - 1, APZ>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
                             Fl);
   };
 
@@ -250,8 +273,11 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
     const bool extra = (E > 0) && le >= 0 && le < E;
     for (int it = 0; it < 2; ++it) {
       if (it == 1 && !extra) break;
-      const int f = (it == 0) ? tid : G::NT + le;
-      const int fa = f % RW, fb = f / RW;
+      // item 0: the face on the low side of the own cell along K; item 1: one
+      // of the faces on the high side of the tile
+      const int fa = (it == 0) ? ox : ((K == 0) ? TX : le);
+      const int fb = (it == 0) ? oy : ((K == 0) ? le : TY);
+      const int f = fb * RW + fa;
       // cell a = (ax, ay), cell b = a + e_K
       const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
       const int bx = fa, by = fb;
@@ -289,7 +315,8 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
       const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
       double Fs, Fl;
-      face_flux<DIM, K>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+      face_flux<DIM, K, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs,
+                             Fl);
       F0[f] = Fs;
       F1[f] = Fl;
     }
@@ -327,7 +354,7 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
       divs += FsU - FsD;
       divl += FlU - FlD;
       double p, q, dp;
-      interp(c, ph, p, q, dp);
+      interp<APZ>(c, ph, p, q, dp);
       const double src = -c.A * (cs - cl) * dp * pt;
       const double ncs = cs + c.dt * (divs * c.inv_dx2 + src);
       const double ncl = cl + c.dt * (divl * c.inv_dx2 + src);

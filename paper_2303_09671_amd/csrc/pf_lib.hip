@@ -154,6 +154,9 @@ int validate(const pf_params& p) {
     for (int k = 0; k < p.dim; ++k)
       if (p.n[k] < 1) return fail(PF_EINVAL, "n[k] must be >= 1");
     if (p.n[p.dim - 1] < 3) return fail(PF_EINVAL, "the growth axis needs at least 3 cells");
+    long long tr = 1;  // cells of one transverse plane: indexed with 32-bit offsets
+    for (int k = 0; k + 1 < p.dim; ++k) tr *= p.n[k];
+    if (tr >= (1LL << 31) - 64) return fail(PF_EINVAL, "a transverse plane must hold fewer than 2^31 cells");
   }
   if (!(p.dx > 0) || !(p.dt > 0) || !(p.W > 0) || !(p.Mphi > 0) || !(p.lambda0 > 0) || !(p.Ds > 0) ||
       !(p.b > 0))
@@ -209,6 +212,9 @@ pfk::Const make_const(const pf_params& p) {
   c.eps2s = c.eps2 * (p.dx * p.dx) * (p.dx * p.dx);
   c.onemA_dx2 = (1.0 - p.A) * p.dx * p.dx;
   c.inv_ke = 1.0 / p.ke;
+  c.W2_dx2 = c.W2 / (p.dx * p.dx);
+  c.eps2r = 16.0 * c.eps2s;
+  c.onemA_4dx2 = 4.0 * c.onemA_dx2;
   return c;
 }
 
@@ -232,16 +238,19 @@ int launch_stream(pf_handle* h, double* const src[3], double* const dst[3], long
   const double tn = (double)n * c.dt;
   const double sn = std::floor(c.V * tn / c.dx);
   const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > sn) ? 1 : 0;
+  const bool apz = (c.ap == 0.0);
   if (c.dim == 3) {
     const int zc = h->zchunk;
     dim3 grid((c.nx + S3_TX - 1) / S3_TX, (c.ny + S3_TY - 1) / S3_TY, (c.nz + zc - 1) / zc);
-    hipLaunchKernelGGL((pfk::k_stream<3, S3_TX, S3_TY>), grid, dim3(S3_TX * S3_TY), 0, h->stream, c, src[0],
-                       src[1], src[2], dst[0], dst[1], dst[2], zc, tn, sn, sh, h->d_err);
+    auto k = apz ? pfk::k_stream<3, S3_TX, S3_TY, true> : pfk::k_stream<3, S3_TX, S3_TY, false>;
+    hipLaunchKernelGGL(k, grid, dim3(S3_TX * S3_TY), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1],
+                       dst[2], zc, tn, sn, sh, h->d_err);
   } else {
     const int zc = h->zchunk;
     dim3 grid((c.nx + S2_TX - 1) / S2_TX, 1, (c.nz + zc - 1) / zc);
-    hipLaunchKernelGGL((pfk::k_stream<2, S2_TX, 1>), grid, dim3(S2_TX), 0, h->stream, c, src[0], src[1], src[2],
-                       dst[0], dst[1], dst[2], zc, tn, sn, sh, h->d_err);
+    auto k = apz ? pfk::k_stream<2, S2_TX, 1, true> : pfk::k_stream<2, S2_TX, 1, false>;
+    hipLaunchKernelGGL(k, grid, dim3(S2_TX), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1], dst[2], zc,
+                       tn, sn, sh, h->d_err);
   }
   PF_HIP(hipGetLastError());
   return PF_OK;

@@ -126,6 +126,26 @@ def test_3d_ragged_with_shift(torch_dev, oracle, periodic):
     assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
 
 
+@pytest.mark.parametrize("dim,quintic,ap", [(2, 1, -2.0), (2, 0, -1.5), (3, 0, 0.0), (3, 1, -2.0)])
+def test_interpolation_variants(torch_dev, oracle, dim, quintic, ap):
+    """Cubic h and a nonzero a_p (Eq. interpolation2) through the 2D/3D step:
+    the step kernels are compiled separately for a_p = 0 and a_p != 0."""
+    if dim == 2:
+        p, _, pert = I.config_2d(nx=70, nz=48)
+        p = dict(p, V=0.5, z0=14 * I.DX)
+    else:
+        p, _, pert = I.config_3d(n=8)
+        p = dict(p, n=(36, 10, 40), V=0.6, z0=14 * I.DX)
+    p = dict(p, quintic=quintic, ap=ap)
+    f = [a.ravel() for a in I.planar_front(dim, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+    steps = 80
+    print(f"case: {dim}D quintic={quintic} ap={ap} steps={steps}", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert ref[3] >= 1
+    assert_parity(g, ref[:3], what=f"{dim}D quintic={quintic} ap={ap}")
+
+
 @pytest.mark.parametrize("which", ["2d", "3d"])
 def test_full_size_one_step(torch_dev, oracle, which):
     """Workload sizes as configured (2D 1024^2, 3D 256^3), same launch
