@@ -30,12 +30,14 @@ using pfk::Const;
 
 constexpr int H = 3;  // box halo
 
-// p, 1-p, p', p'' of the interpolation function.
+// p, 1-p, p', p'' of the interpolation function (APZ: a_p known to be zero).
+template <bool APZ>
 __device__ __forceinline__ void interp2(const Const& c, double phi, double& p, double& q, double& dp, double& d2p) {
-  pfk::interp(c, phi, p, q, dp);
+  pfk::interp<APZ>(c, phi, p, q, dp);
   const double w = phi * (1.0 - phi), t = 1.0 - 2.0 * phi;
   const double d2h = c.quintic ? 60.0 * w * t : 6.0 * t;
-  d2p = d2h + c.ap * (6.0 * w * t - t * t * t);
+  if constexpr (APZ) d2p = d2h;
+  else d2p = d2h + c.ap * (6.0 * w * t - t * t * t);
 }
 
 // Tile geometry: DIM = 1 (growth axis only) or 2 (x transverse, z growth).
@@ -95,13 +97,13 @@ __device__ __forceinline__ void scat(double* a, const Dom& d, int lx, int lz, do
   atomicAdd(&a[G::idx(lx, lz)], v);
 }
 
-template <int DIM>
+template <int DIM, bool APZ>
 __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shift, const double* const* u,
                              const double* const* lam1, double* const* lam0, double* theta_out) {
   using G = Geo<DIM>;
   __shared__ double su[3][G::NB], sl[3][G::NB], spt[G::NB], smu[G::NB];
   __shared__ double au[3][G::NB], amu[G::NB], apt[G::NB];
-  __shared__ double red[4][G::NT];
+  __shared__ double red[4][G::NT / 64];
   const int tid = threadIdx.x;
   const double tn = (double)n * d.dt;
   const double sn = floor(d.V * tn / c.dx);
@@ -176,7 +178,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double gph[DIM], gcs[DIM], gcl[DIM], lap;
     cell_inputs(i, gph, gcs, gcl, lap);
     double pt, mu;
-    pfk::cell_stage<DIM>(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
+    pfk::cell_stage<DIM, APZ>(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
     spt[i] = pt;
   }
   __syncthreads();
@@ -217,7 +219,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       const double Flb = c.dt * c.inv_dx * (sl[2][ia] - sl[2][ib]);
       // recompute the face intermediates
       double p, q, dp;
-      pfk::interp(c, phf, p, q, dp);
+      pfk::interp<APZ>(c, phf, p, q, dp);
       double Gs = 0.0, dmu = 0.0, dcs = 0.0, dcl = 0.0;
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
@@ -229,7 +231,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       const double Ms = c.Ds * csf, Ml = clf;
       const double ms = Ms * q, ml = c.b * Ml * p, Mb = ms + ml;
       const double Sg = Gs * Gs + c.eps2;
-      const double iMS = 1.0 / (Mb * Sg);
+      const double iMS = pfk::frcp(Mb * Sg);  // also 1/Mb = Sg iMS and 1/S = Mb iMS
       const double R = gph[K] * Gs * iMS;  // (grad phi)_K gam / Mbar, gam = G / (G^2 + eps^2)
       const double bq = c.b * p + q;
       const double dcf = csf - clf;
@@ -266,9 +268,9 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       p_b += bq_b * c.b;
       q_b += bq_b;
       // R = gph[K] G / (Mb S), S = G^2 + eps^2
-      double Gs_b = R_b * gph[K] * iMS - R_b * R * 2.0 * Gs / Sg;
+      double Gs_b = R_b * gph[K] * iMS - R_b * R * 2.0 * Gs * (Mb * iMS);
       gph_b[K] += R_b * Gs * iMS;
-      Mb_b += -R_b * R / Mb;
+      Mb_b += -R_b * R * (Sg * iMS);
       ms_b += Mb_b;
       ml_b += Mb_b;
       Ms_b += ms_b * q;
@@ -327,7 +329,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     const double ph = su[0][i], cs = su[1][i], cl = su[2][i];
     const double pt = spt[i];
     double p, q, dp, d2p;
-    interp2(c, ph, p, q, dp, d2p);
+    interp2<APZ>(c, ph, p, q, dp, d2p);
     const double dc = cs - cl;
     // u' = u + dt (div F + src) (c_s, c_l), phi' = phi + dt phi_t; src = -A dc p' phi_t
     const double sb = c.dt * (sl[1][i] + sl[2][i]);
@@ -364,7 +366,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     const double Kd = oA * oA * c.b * dc * dc * pq * Gs;
     const double num = base * Q + c.lambda * X2 + c.lambda * X3;
     const double den = c.alpha * Q + c.lambda * Kd;
-    const double iden = 1.0 / den;
+    const double iden = pfk::frcp(den);
     const double num_b = pt_b * iden;
     const double den_b = -pt_b * num * iden * iden;
     double Q_b = den_b * c.alpha + num_b * base;
@@ -434,8 +436,9 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     p_b += ml_b * c.b * cl;
     cs_b += dc_b;
     cl_b -= dc_b;
-    cs_b += dmu_b / cs;
-    cl_b -= dmu_b / cl;
+    const double icscl = pfk::frcp(cs * cl);
+    cs_b += dmu_b * (cl * icscl);
+    cl_b -= dmu_b * (cs * icscl);
     ph_b += (p_b - q_b) * dp + dp_b * d2p;
     // stencil: central differences and Laplacian
     double gph_b[DIM], gcs_b[DIM], gcl_b[DIM];
@@ -467,31 +470,34 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     if (!owned(lx, lz)) continue;
     const double ph = su[0][i], cs = su[1][i], cl = su[2][i];
     double p, q, dp;
-    pfk::interp(c, ph, p, q, dp);
+    pfk::interp<APZ>(c, ph, p, q, dp);
     const double mb = amu[i];
     const double dmu = pfk::flog(cs) - pfk::flog(cl) - c.log_ke;
     // mu_bar = ln cl + p dmu
+    const double icscl = pfk::frcp(cs * cl);
     const double r0 = sl[0][i] + au[0][i] + mb * dmu * dp;
-    const double r1 = sl[1][i] + au[1][i] + mb * p / cs;
-    const double r2 = sl[2][i] + au[2][i] + mb * (1.0 - p) / cl;
+    const double r1 = sl[1][i] + au[1][i] + mb * p * (cl * icscl);
+    const double r2 = sl[2][i] + au[2][i] + mb * q * (cs * icscl);
     const long long o = d.base + (long long)(d.x0 + lx) + (long long)d.nx * (d.z0 + lz);
     lam0[0][o] = r0;
     lam0[1][o] = r1;
     lam0[2][o] = r2;
   }
-  // ---- parameter cotangents of this block
-  red[0][tid] = thA;
-  red[1][tid] = thAl;
-  red[2][tid] = thLa;
-  red[3][tid] = thW2;
+  // ---- parameter cotangents of this block: a fixed butterfly within each
+  // wave, then the wave sums in wave order (deterministic)
+  double th[4] = {thA, thAl, thLa, thW2};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int m = 32; m > 0; m >>= 1) th[k] += __shfl_xor(th[k], m, 64);
+  if ((tid & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[k][tid >> 6] = th[k];
   __syncthreads();
-  for (int w = G::NT / 2; w > 0; w >>= 1) {
-    if (tid < w)
-      for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + w];
-    __syncthreads();
-  }
   if (tid == 0)
-    for (int k = 0; k < 4; ++k) theta_out[k] = red[k][0];
+    for (int k = 0; k < 4; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < G::NT / 64; ++w) t += red[k][w];
+      theta_out[k] = t;
+    }
 }
 
 // 1D runs (single domain = run 0): block -> (run, tile) from a table.
@@ -499,6 +505,7 @@ struct Tile1 {
   int run, z0;
 };
 
+template <bool APZ>
 __global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Tile1* __restrict__ tiles, long long n,
                                                int do_shift, const double* u0, const double* u1, const double* u2,
                                                const double* l0, const double* l1, const double* l2, double* o0,
@@ -521,9 +528,10 @@ __global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Ti
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<1>(cc, d, n, shift, u, l, o, part + 4 * blockIdx.x);
+  adjoint_tile<1, APZ>(cc, d, n, shift, u, l, o, part + 4 * blockIdx.x);
 }
 
+template <bool APZ>
 __global__ __launch_bounds__(256) void k_adj2d(Const c, long long n, int shift, const double* u0, const double* u1,
                                                const double* u2, const double* l0, const double* l1,
                                                const double* l2, double* o0, double* o1, double* o2,
@@ -541,7 +549,7 @@ __global__ __launch_bounds__(256) void k_adj2d(Const c, long long n, int shift, 
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<2>(c, d, n, shift, u, l, o, part + 4 * (blockIdx.x + gridDim.x * blockIdx.y));
+  adjoint_tile<2, APZ>(c, d, n, shift, u, l, o, part + 4 * (blockIdx.x + gridDim.x * blockIdx.y));
 }
 
 // Sum the block partials in block order and add the cotangents of

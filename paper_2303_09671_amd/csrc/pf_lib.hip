@@ -577,16 +577,19 @@ int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const d
     if (rc) return rc;
     h->ntheta_part = nblk;
   }
+  const bool apz = (c.ap == 0.0);
   if (h->batched) {
-    hipLaunchKernelGGL(pfadj::k_adj1d, dim3(nblk), dim3(256), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n,
-                       h->p.shift, u_n[0], u_n[1], u_n[2], lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1],
-                       lam_n[2], h->d_theta_part);
+    auto k = apz ? pfadj::k_adj1d<true> : pfadj::k_adj1d<false>;
+    hipLaunchKernelGGL(k, dim3(nblk), dim3(256), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n, h->p.shift,
+                       u_n[0], u_n[1], u_n[2], lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2],
+                       h->d_theta_part);
   } else {
     const double tn = (double)n * c.dt;
     const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > std::floor(c.V * tn / c.dx));
     dim3 grid((c.nx + pfadj::Geo<2>::TX - 1) / pfadj::Geo<2>::TX, (c.nz + pfadj::Geo<2>::TZ - 1) / pfadj::Geo<2>::TZ);
-    hipLaunchKernelGGL(pfadj::k_adj2d, grid, dim3(256), 0, h->stream, c, (long long)n, sh, u_n[0], u_n[1], u_n[2],
-                       lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2], h->d_theta_part);
+    auto k = apz ? pfadj::k_adj2d<true> : pfadj::k_adj2d<false>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, h->stream, c, (long long)n, sh, u_n[0], u_n[1], u_n[2], lam_np1[0],
+                       lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2], h->d_theta_part);
   }
   PF_HIP(hipGetLastError());
   hipLaunchKernelGGL(pfadj::k_theta_final, dim3(1), dim3(256), 0, h->stream, c, h->d_theta_part, nblk, dtheta);

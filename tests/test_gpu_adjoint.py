@@ -81,13 +81,14 @@ def _transpose_check(torch, oracle, p, fields, n, s, seed, runs=None, offsets=No
         assert abs(g_theta[i] - ref) <= 1e-10 * sc + 1e-14, (i, g_theta[i], ref, sc)
 
 
-@pytest.mark.parametrize("nstep", [40, 62])  # step 62 -> 63 shifts the window (V dt / dx = 1/62.5)
-def test_transpose_1d(torch_dev, oracle, nstep):
+# step 62 -> 63 shifts the window (V dt / dx = 1/62.5)
+@pytest.mark.parametrize("nstep,quintic,ap", [(40, 1, 0.0), (62, 1, 0.0), (62, 0, -1.5)])
+def test_transpose_1d(torch_dev, oracle, nstep, quintic, ap):
     p, _ = I.config_1d(N=160)
-    p = dict(p, z0=50 * I.DX)
+    p = dict(p, z0=50 * I.DX, quintic=quintic, ap=ap)
     f0 = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
     f = oracle.step(oracle_params(oracle, p), *f0, nstep)
-    print(f"case: 1D transpose n={nstep}", flush=True)
+    print(f"case: 1D transpose n={nstep} quintic={quintic} ap={ap}", flush=True)
     _transpose_check(torch_dev, oracle, p, f[:3], nstep, f[3], seed=nstep)
 
 
@@ -109,14 +110,19 @@ def test_transpose_batch(torch_dev, oracle):
     _transpose_check(torch_dev, oracle, base, state, nstep, None, seed=5, runs=runs, offsets=offs, oracle_runs=oruns)
 
 
-@pytest.mark.parametrize("periodic,nx,V", [(1, 24, 0.05), (0, 20, 0.8), (1, 40, 0.8)])
-def test_transpose_2d(torch_dev, oracle, periodic, nx, V):
+@pytest.mark.parametrize("periodic,nx,V,quintic,ap", [(1, 24, 0.05, 1, 0.0), (0, 20, 0.8, 1, 0.0),
+                                                      (1, 40, 0.8, 1, 0.0), (0, 20, 0.8, 0, -1.5),
+                                                      (1, 24, 0.8, 1, -2.0)])
+def test_transpose_2d(torch_dev, oracle, periodic, nx, V, quintic, ap):
+    """Also cubic h and a_p != 0 (the adjoint kernels are compiled separately
+    for a_p = 0 and a_p != 0)."""
     p, _, pert = I.config_2d(nx=nx, nz=48)
-    p = dict(p, periodic=(periodic, 0, 0), V=V, z0=14 * I.DX)
+    p = dict(p, periodic=(periodic, 0, 0), V=V, z0=14 * I.DX, quintic=quintic, ap=ap)
     f0 = [a.ravel() for a in I.planar_front(2, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=3)]
     nstep = 31  # with V = 0.8 the step 31 -> 32 shifts the window (V dt / dx = 1/31.25)
     f = oracle.step(oracle_params(oracle, p), *f0, nstep)
-    print(f"case: 2D transpose periodic={periodic} nx={nx} V={V} shift_count={f[3]}", flush=True)
+    print(f"case: 2D transpose periodic={periodic} nx={nx} V={V} quintic={quintic} ap={ap} shift_count={f[3]}",
+          flush=True)
     _transpose_check(torch_dev, oracle, p, f[:3], nstep, f[3], seed=7)
 
 
