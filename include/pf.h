@@ -130,10 +130,25 @@ int pf_check(pf_handle* h);
  * with alpha = W / M_phi and lambda = lambda0 W (gamma, Omega, D and the grid
  * fixed).  u_n[f], lam_np1[f], lam_n[f] (f = phi, c_s, c_l) are device arrays
  * in the field layout; lam_n may not alias lam_np1.  dtheta is a device
- * double[3], accumulated.  The gate branches and the window shift of step n
- * are held fixed (piecewise constant).  Asynchronous on the stream. */
+ * double[3], accumulated.  The window shift of step n is held fixed (it is
+ * piecewise constant in theta).  Built for 1D runs and 2D grids (3D:
+ * PF_EINVAL).  Asynchronous on the stream. */
 int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
                     double* const lam_n[3], double* dtheta);
+
+/* The adjoint over a checkpoint segment: m steps of pf_adjoint_step taken
+ * backwards, n = n0 + m - 1 down to n0, in one call.  Row j (j = 0..m-1) of the
+ * device trajectory traj_*[j * stride + i] holds the state at step n0 + j (as
+ * written by pf_step_traj; stride >= the field size).  On entry lam[f] holds
+ * lam^{n0+m}, on return lam^{n0}; work[f] are caller-owned device arrays of the
+ * field size used for the ping-pong (contents undefined afterwards; they may
+ * not alias lam).  dtheta (device double[3]) is accumulated once for the whole
+ * segment: the per-block sums are carried over the m steps and reduced at the
+ * end, so the result equals the sum of m pf_adjoint_step calls up to rounding
+ * order.  Asynchronous on the stream. */
+int pf_adjoint_segment(pf_handle* h, int64_t n0, int64_t m, const double* traj_phi, const double* traj_cs,
+                       const double* traj_cl, int64_t stride, double* const lam[3], double* const work[3],
+                       double* dtheta);
 
 /* Adjoint seed of the partition-coefficient loss: for every run r (or the
  * single domain) with k_r = 1 / c_max, writes lam[f] = sum_r dL_dk[r] dk_r/du[f]

@@ -6,9 +6,10 @@ theta = (A, M_phi, W), through the C ABI's adjoint step.
 a checkpoint every ``workload.every`` steps, and returns k per run (k of
 Sec. V.C: 1 / max c with c = p c_s + (1-p) c_l).  Its backward seeds the
 adjoint at the final state with dL/dk (pf_kv_seed), then for each checkpoint
-segment in reverse replays the segment's states (pf_step_traj) and applies the
-adjoint step backwards over them (pf_adjoint_step), accumulating dL/dtheta on
-the device.  Torch supplies device memory and the stream only.
+segment in reverse replays the segment's states (pf_step_traj) and takes the
+adjoint steps backwards over them in one call (pf_adjoint_segment),
+accumulating dL/dtheta on the device.  Torch supplies device memory and the
+stream only.
 """
 from __future__ import annotations
 
@@ -76,43 +77,21 @@ class PartitionCoefficient(torch.autograd.Function):
     def backward(ctx, grad_k):
         h, fields, ck = ctx.state
         wl = ctx.workload
-        nfield = fields[0].numel()
         lam = [torch.empty_like(fields[0]) for _ in range(3)]
-        lam2 = [torch.empty_like(fields[0]) for _ in range(3)]
         pf.pf_kv_seed(h, grad_k.detach().cpu().numpy().astype(np.float64), lam)
-        dtheta = torch.zeros(3, dtype=torch.float64, device=fields[0].device)
-        K = wl.every
-        traj = [torch.empty((K + 1, nfield), dtype=torch.float64, device=fields[0].device) for _ in range(3)]
-        nseg = len(ck)
-        for s in reversed(range(nseg)):
-            n0 = s * K
-            m = min(K, wl.nsteps - n0)
-            for f, c in zip(fields, ck[s]):
-                f.copy_(c)
-            pf.pf_set_step(h, n0)
-            pf.pf_step_traj(h, m, traj)
-            for j in reversed(range(m)):
-                u = [traj[f][j] for f in range(3)]
-                pf.pf_adjoint_step(h, n0 + j, u, lam, lam2, dtheta)
-                lam, lam2 = lam2, lam
+        dtheta = _backward_segments(h, wl, fields, ck, lam)
         ctx.state = None
         return dtheta.cpu(), None
 
 
-def adjoint_only_seconds(workload: Workload, theta, nsteps: int | None = None) -> float:
-    """Wall time of the backward pass alone (replay + adjoint) for timing."""
-    import time
-    k, h, fields, ck = forward_k(workload, theta, checkpoints=True)
-    wl = workload
+def _backward_segments(h, wl: Workload, fields, ck, lam):
+    """Replay each checkpoint segment in reverse and take its adjoint steps;
+    lam holds the cotangent of the final state on entry.  Returns dL/dtheta."""
     nfield = fields[0].numel()
-    lam = [torch.zeros_like(fields[0]) for _ in range(3)]
-    lam2 = [torch.empty_like(fields[0]) for _ in range(3)]
-    pf.pf_kv_seed(h, np.ones(wl.nrun), lam)
+    work = [torch.empty_like(fields[0]) for _ in range(3)]
     dtheta = torch.zeros(3, dtype=torch.float64, device=fields[0].device)
     K = wl.every
     traj = [torch.empty((K + 1, nfield), dtype=torch.float64, device=fields[0].device) for _ in range(3)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for s in reversed(range(len(ck))):
         n0 = s * K
         m = min(K, wl.nsteps - n0)
@@ -120,8 +99,18 @@ def adjoint_only_seconds(workload: Workload, theta, nsteps: int | None = None) -
             f.copy_(c)
         pf.pf_set_step(h, n0)
         pf.pf_step_traj(h, m, traj)
-        for j in reversed(range(m)):
-            pf.pf_adjoint_step(h, n0 + j, [traj[f][j] for f in range(3)], lam, lam2, dtheta)
-            lam, lam2 = lam2, lam
+        pf.pf_adjoint_segment(h, n0, m, traj, lam, work, dtheta)
+    return dtheta
+
+
+def adjoint_only_seconds(workload: Workload, theta, nsteps: int | None = None) -> float:
+    """Wall time of the backward pass alone (replay + adjoint) for timing."""
+    import time
+    k, h, fields, ck = forward_k(workload, theta, checkpoints=True)
+    lam = [torch.zeros_like(fields[0]) for _ in range(3)]
+    pf.pf_kv_seed(h, np.ones(workload.nrun), lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _backward_segments(h, workload, fields, ck, lam)
     torch.cuda.synchronize()
     return time.perf_counter() - t0

@@ -44,7 +44,7 @@ __device__ __forceinline__ void interp2(const Const& c, double phi, double& p, d
 template <int DIM>
 struct Geo {
   static constexpr int TX = (DIM == 2) ? 16 : 1;
-  static constexpr int TZ = (DIM == 2) ? 16 : 128;
+  static constexpr int TZ = (DIM == 2) ? 16 : 250;  // 1D: box of 256 cells, one per thread
   static constexpr int BX = (DIM == 2) ? TX + 2 * H : 1;
   static constexpr int BZ = TZ + 2 * H;
   static constexpr int NB = BX * BZ;
@@ -99,10 +99,12 @@ __device__ __forceinline__ void scat(double* a, const Dom& d, int lx, int lz, do
 
 template <int DIM, bool APZ>
 __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shift, const double* const* u,
-                             const double* const* lam1, double* const* lam0, double* theta_out) {
+                             const double* const* lam1, double* const* lam0, double* theta_out, int accum) {
   using G = Geo<DIM>;
   __shared__ double su[3][G::NB], sl[3][G::NB], spt[G::NB], smu[G::NB];
   __shared__ double au[3][G::NB], amu[G::NB], apt[G::NB];
+  // 1D: (mu_s - mu_l)/Omega of the box, computed once (2D: recomputed; no LDS room)
+  __shared__ double sdm[(DIM == 1) ? G::NB : 1];
   __shared__ double red[4][G::NT / 64];
   const int tid = threadIdx.x;
   const double tn = (double)n * d.dt;
@@ -127,7 +129,14 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     amu[i] = 0.0;
     apt[i] = 0.0;
     spt[i] = 0.0;
-    smu[i] = pfk::mubar_of(c, su[0][i], su[1][i], su[2][i]);  // pointwise: whole box
+    {  // mu_bar, pointwise: whole box
+      double p, q;
+      pfk::interp_pq<APZ>(c, su[0][i], p, q);
+      const double ll = pfk::flog(su[2][i]);
+      const double dm = pfk::flog(su[1][i]) - ll - c.log_ke;
+      smu[i] = ll + p * dm;
+      if constexpr (DIM == 1) sdm[i] = dm;
+    }
   }
   __syncthreads();
 
@@ -177,8 +186,17 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     if (!in_box(lx, lz, 2)) continue;
     double gph[DIM], gcs[DIM], gcl[DIM], lap;
     cell_inputs(i, gph, gcs, gcl, lap);
-    double pt, mu;
-    pfk::cell_stage<DIM, APZ>(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
+    double pt;
+    if constexpr (DIM == 1) {
+      double p, q, dp;
+      pfk::interp<APZ>(c, su[0][i], p, q, dp);
+      const double G = gph[0] * gph[0], dot = (c.Ds * gcs[0] - c.b * gcl[0]) * gph[0];
+      pt = pfk::cell_rate(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], sdm[i], p, q, dp, G, dot, c.W2 * lap,
+                          c.eps2, c.onemA);
+    } else {
+      double mu;
+      pfk::cell_stage<DIM, APZ>(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
+    }
     spt[i] = pt;
   }
   __syncthreads();
@@ -343,8 +361,9 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double gph[DIM], gcs[DIM], gcl[DIM], lap;
     cell_inputs(i, gph, gcs, gcl, lap);
     const double cleq = cleq_of_lz(lz);
-    const double ll = pfk::flog(cl);
-    const double dmu = pfk::flog(cs) - ll - c.log_ke;
+    double dmu;
+    if constexpr (DIM == 1) dmu = sdm[i];
+    else dmu = pfk::flog(cs) - pfk::flog(cl) - c.log_ke;
     const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;
     const double ms = c.Ds * cs * q, ml = c.b * cl * p, Mb = ms + ml;
     const double Dn = ms * (1.0 - c.A * q) + c.A * ml * p;
@@ -472,7 +491,9 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double p, q, dp;
     pfk::interp<APZ>(c, ph, p, q, dp);
     const double mb = amu[i];
-    const double dmu = pfk::flog(cs) - pfk::flog(cl) - c.log_ke;
+    double dmu;
+    if constexpr (DIM == 1) dmu = sdm[i];
+    else dmu = pfk::flog(cs) - pfk::flog(cl) - c.log_ke;
     // mu_bar = ln cl + p dmu
     const double icscl = pfk::frcp(cs * cl);
     const double r0 = sl[0][i] + au[0][i] + mb * dmu * dp;
@@ -496,7 +517,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     for (int k = 0; k < 4; ++k) {
       double t = 0.0;
       for (int w = 0; w < G::NT / 64; ++w) t += red[k][w];
-      theta_out[k] = t;
+      theta_out[k] = accum ? theta_out[k] + t : t;  // accum: sum over the steps of a segment
     }
 }
 
@@ -509,7 +530,7 @@ template <bool APZ>
 __global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Tile1* __restrict__ tiles, long long n,
                                                int do_shift, const double* u0, const double* u1, const double* u2,
                                                const double* l0, const double* l1, const double* l2, double* o0,
-                                               double* o1, double* o2, double* __restrict__ part) {
+                                               double* o1, double* o2, double* __restrict__ part, int accum) {
   const Tile1 t = tiles[blockIdx.x];
   Dom d;
   d.nx = 1;
@@ -528,14 +549,14 @@ __global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Ti
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<1, APZ>(cc, d, n, shift, u, l, o, part + 4 * blockIdx.x);
+  adjoint_tile<1, APZ>(cc, d, n, shift, u, l, o, part + 4 * blockIdx.x, accum);
 }
 
 template <bool APZ>
 __global__ __launch_bounds__(256) void k_adj2d(Const c, long long n, int shift, const double* u0, const double* u1,
                                                const double* u2, const double* l0, const double* l1,
                                                const double* l2, double* o0, double* o1, double* o2,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, int accum) {
   Dom d;
   d.nx = c.nx;
   d.nz = c.nz;
@@ -549,7 +570,7 @@ __global__ __launch_bounds__(256) void k_adj2d(Const c, long long n, int shift, 
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<2, APZ>(c, d, n, shift, u, l, o, part + 4 * (blockIdx.x + gridDim.x * blockIdx.y));
+  adjoint_tile<2, APZ>(c, d, n, shift, u, l, o, part + 4 * (blockIdx.x + gridDim.x * blockIdx.y), accum);
 }
 
 // Sum the block partials in block order and add the cotangents of

@@ -151,15 +151,11 @@ __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs
 // in units where the true values are k G and k dot, with eps2x = eps^2 / k^2 and
 // onemAx = (1 - A) / k (the common factor k^2 of numerator and prefactor cancels);
 // Wlap is W^2 lap.
-template <bool APZ>
-__device__ __forceinline__ void cell_core(const Const& c, double cleq, double phi, double cs, double cl, double G,
-                                          double dot, double Wlap, double eps2x, double onemAx, double& phit,
-                                          double& mubar) {
-  double p, q, dp;
-  interp<APZ>(c, phi, p, q, dp);
-  const double ll = flog(cl);
-  const double dmu = flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
-  mubar = ll + p * dmu;
+// phi_t from the interpolation values p, q = 1-p, p', dmu = (mu_s - mu_l)/Omega
+// and the scaled G, dot (see cell_core).
+__device__ __forceinline__ double cell_rate(const Const& c, double cleq, double phi, double cs, double cl, double dmu,
+                                           double p, double q, double dp, double G, double dot, double Wlap,
+                                           double eps2x, double onemAx) {
   const double dc = cs - cl;
   const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;  // Eq. dil5.2 with Eq. ds3
   const double ms = c.Ds * cs * q;                          // M_s (1 - p)
@@ -175,7 +171,19 @@ __device__ __forceinline__ void cell_core(const Const& c, double cleq, double ph
   const double base = Wlap - fdw - c.lambda * dGc * dp;
   const double num = base * Q + c.lambda * Dn * dc * dmu * dp * bq * S + lAdc * pq * dot * G * bq;
   const double den = c.alpha * Q + lAdc * onemAx * dc * c.b * pq * G;
-  phit = num * frcp(den);
+  return num * frcp(den);
+}
+
+template <bool APZ>
+__device__ __forceinline__ void cell_core(const Const& c, double cleq, double phi, double cs, double cl, double G,
+                                          double dot, double Wlap, double eps2x, double onemAx, double& phit,
+                                          double& mubar) {
+  double p, q, dp;
+  interp<APZ>(c, phi, p, q, dp);
+  const double ll = flog(cl);
+  const double dmu = flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
+  mubar = ll + p * dmu;
+  phit = cell_rate(c, cleq, phi, cs, cl, dmu, p, q, dp, G, dot, Wlap, eps2x, onemAx);
 }
 
 // g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the

@@ -409,15 +409,15 @@ struct RunTab {
   const int* order;  // launch order (longest first)
 };
 
-__global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double* __restrict__ gph,
-                                                      double* __restrict__ gcs, double* __restrict__ gcl,
-                                                      long long n0, long long nsteps, int do_shift,
-                                                      int* __restrict__ err, double* __restrict__ tph,
-                                                      double* __restrict__ tcs, double* __restrict__ tcl,
-                                                      long long tstride) {
-  __shared__ double xe[2][3][R1_THREADS];  // [first|last][phi, cs, cl][thread]
-  __shared__ double xd[2][2][R1_THREADS];  // [first|last][phi_t, mu_bar][thread]
-  const int r = rt.order[blockIdx.x];
+// One run (the block's) for nsteps steps; CM >= ceil(N / R1_THREADS) cells per
+// thread are held in registers.  xe/xd are the block's exchange buffers.
+template <int CM, bool APZ>
+__device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int r, double* __restrict__ gph,
+                                           double* __restrict__ gcs, double* __restrict__ gcl, long long n0,
+                                           long long nsteps, int do_shift, int* __restrict__ err,
+                                           double* __restrict__ tph, double* __restrict__ tcs,
+                                           double* __restrict__ tcl, long long tstride,
+                                           double (*xe)[3][R1_THREADS], double (*xd)[2][R1_THREADS]) {
   const int N = rt.n[r];
   const long long off = rt.off[r];
   const double V = rt.V[r], dt = rt.dt[r], z0 = rt.z0[r];
@@ -429,16 +429,16 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
   const bool at_hi = (cnt > 0) && (i0 + cnt == N);
   const bool has_right = (cnt > 0) && !at_hi;  // thread t+1 owns cell i0 + cnt
 
-  double P[R1_CMAX], S[R1_CMAX], L[R1_CMAX];
+  double P[CM], S[CM], L[CM];
   // value of register array a at runtime position idx (static selects, no scratch)
-  auto pick = [](const double (&a)[R1_CMAX], int idx) {
+  auto pick = [](const double (&a)[CM], int idx) {
     double v = a[0];
 #pragma unroll
-    for (int k = 1; k < R1_CMAX; ++k) v = (k == idx) ? a[k] : v;
+    for (int k = 1; k < CM; ++k) v = (k == idx) ? a[k] : v;
     return v;
   };
 #pragma unroll
-  for (int k = 0; k < R1_CMAX; ++k) {
+  for (int k = 0; k < CM; ++k) {
     if (k < cnt) {
       P[k] = gph[off + i0 + k];
       S[k] = gcs[off + i0 + k];
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
     const long long n = n0 + st;
     if (tph) {
 #pragma unroll
-      for (int k = 0; k < R1_CMAX; ++k)
+      for (int k = 0; k < CM; ++k)
         if (k < cnt) {
           const long long o = st * tstride + off + i0 + k;
           tph[o] = P[k];
@@ -496,22 +496,22 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
       rL = pick(L, cnt - 1);
     }
     // cell stage
-    double PT[R1_CMAX], MU[R1_CMAX];
+    double PT[CM], MU[CM];
 #pragma unroll
-    for (int k = 0; k < R1_CMAX; ++k) {
+    for (int k = 0; k < CM; ++k) {
       PT[k] = 0.0;
       MU[k] = 0.0;
       if (k < cnt) {
-        const double pm = (k == 0) ? lP : P[k - 1], pp = (k == cnt - 1) ? rP : P[(k + 1 < R1_CMAX) ? k + 1 : k];
-        const double sm = (k == 0) ? lS : S[k - 1], sp = (k == cnt - 1) ? rS : S[(k + 1 < R1_CMAX) ? k + 1 : k];
-        const double lm = (k == 0) ? lL : L[k - 1], lp = (k == cnt - 1) ? rL : L[(k + 1 < R1_CMAX) ? k + 1 : k];
-        double gph1[1] = {(pp - pm) * c.inv_2dx};
-        double gcs1[1] = {(sp - sm) * c.inv_2dx};
-        double gcl1[1] = {(lp - lm) * c.inv_2dx};
-        const double lap = (pp - 2.0 * P[k] + pm) * c.inv_dx2;
+        const double pm = (k == 0) ? lP : P[k - 1], pp = (k == cnt - 1) ? rP : P[(k + 1 < CM) ? k + 1 : k];
+        const double sm = (k == 0) ? lS : S[k - 1], sp = (k == cnt - 1) ? rS : S[(k + 1 < CM) ? k + 1 : k];
+        const double lm = (k == 0) ? lL : L[k - 1], lp = (k == cnt - 1) ? rL : L[(k + 1 < CM) ? k + 1 : k];
+        double gph1[1] = {pp - pm};  // plain differences (cell_stage_raw)
+        double gcs1[1] = {sp - sm};
+        double gcl1[1] = {lp - lm};
+        const double lap = pp - 2.0 * P[k] + pm;
         const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
         const double cleq = cleq_at(c, zlab, tn, V, z0);
-        cell_stage<1>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
+        cell_stage_raw<1, APZ>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
       }
     }
     // exchange 2: phi_t and mu_bar of the chunk edges
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
       double pa = lP, sa = lS, la = lL, ta = lPT, ma = lMU;
       double pb = rP, sb = rS, lb = rL, tb = rPT, mb = rMU;
 #pragma unroll
-      for (int k = 0; k < R1_CMAX; ++k) {
+      for (int k = 0; k < CM; ++k) {
         if (k == j - 1) {
           pa = P[k];
           sa = S[k];
@@ -556,17 +556,18 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
       double g1[1] = {mb - ma};
       double g2[1] = {sb - sa};
       double g3[1] = {lb - la};
-      face_flux<1, 0>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3, Fs, Fl);
+      face_flux<1, 0, APZ>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3, Fs,
+                           Fl);
     };
     double FsL, FlL;
     face(0, FsL, FlL);
 #pragma unroll
-    for (int k = 0; k < R1_CMAX; ++k) {
+    for (int k = 0; k < CM; ++k) {
       if (k < cnt) {
         double FsR, FlR;
         face(k + 1, FsR, FlR);
         double p, q, dp;
-        interp(c, P[k], p, q, dp);
+        interp<APZ>(c, P[k], p, q, dp);
         const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
         const double ns = S[k] + dt * ((FsR - FsL) * c.inv_dx2 + src);
         const double nl = L[k] + dt * ((FlR - FlL) * c.inv_dx2 + src);
@@ -598,25 +599,47 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
         nL = 1.0;
       }
 #pragma unroll
-      for (int k = 0; k < R1_CMAX; ++k) {
+      for (int k = 0; k < CM; ++k) {
         if (k < cnt) {
           const bool last = (k == cnt - 1);
-          P[k] = last ? nP : P[(k + 1 < R1_CMAX) ? k + 1 : k];
-          S[k] = last ? nS : S[(k + 1 < R1_CMAX) ? k + 1 : k];
-          L[k] = last ? nL : L[(k + 1 < R1_CMAX) ? k + 1 : k];
+          P[k] = last ? nP : P[(k + 1 < CM) ? k + 1 : k];
+          S[k] = last ? nS : S[(k + 1 < CM) ? k + 1 : k];
+          L[k] = last ? nL : L[(k + 1 < CM) ? k + 1 : k];
         }
       }
     }
     __syncthreads();  // exchange buffers are rewritten by the next step
   }
 #pragma unroll
-  for (int k = 0; k < R1_CMAX; ++k)
+  for (int k = 0; k < CM; ++k)
     if (k < cnt) {
       gph[off + i0 + k] = P[k];
       gcs[off + i0 + k] = S[k];
       gcl[off + i0 + k] = L[k];
     }
   if (errbits) atomicOr(err, errbits);
+}
+
+template <bool APZ>
+__global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double* __restrict__ gph,
+                                                      double* __restrict__ gcs, double* __restrict__ gcl,
+                                                      long long n0, long long nsteps, int do_shift,
+                                                      int* __restrict__ err, double* __restrict__ tph,
+                                                      double* __restrict__ tcs, double* __restrict__ tcl,
+                                                      long long tstride) {
+  __shared__ double xe[2][3][R1_THREADS];  // [first|last][phi, cs, cl][thread]
+  __shared__ double xd[2][2][R1_THREADS];  // [first|last][phi_t, mu_bar][thread]
+  const int r = rt.order[blockIdx.x];
+  const int C = (rt.n[r] + R1_THREADS - 1) / R1_THREADS;
+  // register arrays sized to the run: short runs get short unrolled loops
+  if (C <= 1)
+    run1d_body<1, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+  else if (C <= 2)
+    run1d_body<2, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+  else if (C <= 4)
+    run1d_body<4, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+  else
+    run1d_body<R1_CMAX, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
 }
 
 // ---------------------------------------------------------------------------

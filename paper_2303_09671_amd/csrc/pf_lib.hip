@@ -423,7 +423,8 @@ static int step_impl(pf_handle* h, int64_t nsteps, double* const traj[3], int64_
       double* t0 = traj[0] ? traj[0] + done * stride : nullptr;
       double* t1 = traj[1] ? traj[1] + done * stride : nullptr;
       double* t2 = traj[2] ? traj[2] + done * stride : nullptr;
-      hipLaunchKernelGGL(pfk::k_run1d, dim3(h->nrun), dim3(pfk::R1_THREADS), 0, h->stream, h->c, h->runtab(),
+      auto k = (h->c.ap == 0.0) ? pfk::k_run1d<true> : pfk::k_run1d<false>;
+      hipLaunchKernelGGL(k, dim3(h->nrun), dim3(pfk::R1_THREADS), 0, h->stream, h->c, h->runtab(),
                          h->f[0], h->f[1], h->f[2], (long long)(h->n + done), chunk, h->p.shift, h->d_err, t0, t1,
                          t2, (long long)stride);
       PF_HIP(hipGetLastError());
@@ -440,15 +441,37 @@ static int step_impl(pf_handle* h, int64_t nsteps, double* const traj[3], int64_
     h->n += nsteps;
     return PF_OK;
   }
-  // 2D / 3D: one fused launch per step, ping-pong between the caller's fields and the twin
+  // 2D / 3D: one fused launch per step.  Without a trajectory: ping-pong
+  // between the caller's fields and the twin.  With one: each step reads
+  // trajectory row s and writes row s + 1, and the caller's fields receive the
+  // newest row at the end (or when a check fails).
+  const size_t bytes = (size_t)h->ntot * sizeof(double);
+  if (traj[0]) {
+    for (int k = 0; k < 3; ++k)
+      PF_HIP(hipMemcpyAsync(traj[k], h->f[k], bytes, hipMemcpyDeviceToDevice, h->stream));
+    long long s = 0;
+    int rc = PF_OK;
+    for (; s < nsteps; ++s) {
+      double* src[3] = {traj[0] + s * stride, traj[1] + s * stride, traj[2] + s * stride};
+      double* dst[3] = {traj[0] + (s + 1) * stride, traj[1] + (s + 1) * stride, traj[2] + (s + 1) * stride};
+      rc = launch_stream(h, src, dst, h->n + s);
+      if (rc) return rc;
+      if (h->p.check_every > 0 && ((s + 1) % h->p.check_every == 0)) {
+        rc = read_err(h, false);
+        if (rc) {
+          ++s;
+          break;
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k)
+      PF_HIP(hipMemcpyAsync(h->f[k], traj[k] + s * stride, bytes, hipMemcpyDeviceToDevice, h->stream));
+    h->n += s;
+    return rc;
+  }
   double* cur[3] = {h->f[0], h->f[1], h->f[2]};
   double* nxt[3] = {h->tw[0], h->tw[1], h->tw[2]};
-  const size_t bytes = (size_t)h->ntot * sizeof(double);
   for (long long s = 0; s < nsteps; ++s) {
-    if (traj[0]) {
-      for (int k = 0; k < 3; ++k)
-        PF_HIP(hipMemcpyAsync(traj[k] + s * stride, cur[k], bytes, hipMemcpyDeviceToDevice, h->stream));
-    }
     int rc = launch_stream(h, cur, nxt, h->n + s);
     if (rc) return rc;
     for (int k = 0; k < 3; ++k) std::swap(cur[k], nxt[k]);
@@ -466,10 +489,6 @@ static int step_impl(pf_handle* h, int64_t nsteps, double* const traj[3], int64_
   }
   if (cur[0] != h->f[0]) {
     for (int k = 0; k < 3; ++k) PF_HIP(hipMemcpyAsync(h->f[k], cur[k], bytes, hipMemcpyDeviceToDevice, h->stream));
-  }
-  if (traj[0]) {
-    for (int k = 0; k < 3; ++k)
-      PF_HIP(hipMemcpyAsync(traj[k] + nsteps * stride, h->f[k], bytes, hipMemcpyDeviceToDevice, h->stream));
   }
   h->n += nsteps;
   return PF_OK;
@@ -543,14 +562,8 @@ int pf_kv_seed(pf_handle* h, const double* dL_dk, double* const lam[3]) {
   return PF_OK;
 }
 
-int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
-                    double* const lam_n[3], double* dtheta) {
-  if (!h || !u_n || !lam_np1 || !lam_n || !dtheta || n < 0) return fail(PF_EINVAL, "null argument");
-  for (int k = 0; k < 3; ++k) {
-    if (!u_n[k] || !lam_np1[k] || !lam_n[k]) return fail(PF_EINVAL, "null field pointer");
-    for (int j = 0; j < 3; ++j)
-      if (lam_n[k] == lam_np1[j]) return fail(PF_EINVAL, "lam_n may not alias lam_np1");
-  }
+// Tiles and partial-sum buffer of the adjoint launches; returns the block count.
+static int adj_prepare(pf_handle* h, int* nblk_out) {
   const pfk::Const& c = h->c;
   int nblk = 0;
   if (h->batched) {
@@ -577,22 +590,84 @@ int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const d
     if (rc) return rc;
     h->ntheta_part = nblk;
   }
+  *nblk_out = nblk;
+  return PF_OK;
+}
+
+// One adjoint-step launch; block partials of the parameter cotangents are
+// written (accum = 0) or added (accum = 1) to the partial-sum buffer.
+static int adj_launch(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
+                      double* const lam_n[3], int nblk, int accum) {
+  const pfk::Const& c = h->c;
   const bool apz = (c.ap == 0.0);
   if (h->batched) {
     auto k = apz ? pfadj::k_adj1d<true> : pfadj::k_adj1d<false>;
     hipLaunchKernelGGL(k, dim3(nblk), dim3(256), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n, h->p.shift,
                        u_n[0], u_n[1], u_n[2], lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2],
-                       h->d_theta_part);
+                       h->d_theta_part, accum);
   } else {
     const double tn = (double)n * c.dt;
     const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > std::floor(c.V * tn / c.dx));
     dim3 grid((c.nx + pfadj::Geo<2>::TX - 1) / pfadj::Geo<2>::TX, (c.nz + pfadj::Geo<2>::TZ - 1) / pfadj::Geo<2>::TZ);
     auto k = apz ? pfadj::k_adj2d<true> : pfadj::k_adj2d<false>;
     hipLaunchKernelGGL(k, grid, dim3(256), 0, h->stream, c, (long long)n, sh, u_n[0], u_n[1], u_n[2], lam_np1[0],
-                       lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2], h->d_theta_part);
+                       lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2], h->d_theta_part, accum);
   }
   PF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(pfadj::k_theta_final, dim3(1), dim3(256), 0, h->stream, c, h->d_theta_part, nblk, dtheta);
+  return PF_OK;
+}
+
+static bool any_alias(const double* const a[3], const double* const b[3]) {
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      if (a[k] == b[j]) return true;
+  return false;
+}
+
+int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
+                    double* const lam_n[3], double* dtheta) {
+  if (!h || !u_n || !lam_np1 || !lam_n || !dtheta || n < 0) return fail(PF_EINVAL, "null argument");
+  for (int k = 0; k < 3; ++k)
+    if (!u_n[k] || !lam_np1[k] || !lam_n[k]) return fail(PF_EINVAL, "null field pointer");
+  const double* const l0c[3] = {lam_n[0], lam_n[1], lam_n[2]};
+  if (any_alias(l0c, lam_np1)) return fail(PF_EINVAL, "lam_n may not alias lam_np1");
+  int nblk = 0;
+  int rc = adj_prepare(h, &nblk);
+  if (rc) return rc;
+  if ((rc = adj_launch(h, n, u_n, lam_np1, lam_n, nblk, 0))) return rc;
+  hipLaunchKernelGGL(pfadj::k_theta_final, dim3(1), dim3(256), 0, h->stream, h->c, h->d_theta_part, nblk, dtheta);
+  PF_HIP(hipGetLastError());
+  return PF_OK;
+}
+
+int pf_adjoint_segment(pf_handle* h, int64_t n0, int64_t m, const double* traj_phi, const double* traj_cs,
+                       const double* traj_cl, int64_t stride, double* const lam[3], double* const work[3],
+                       double* dtheta) {
+  if (!h || !traj_phi || !traj_cs || !traj_cl || !lam || !work || !dtheta || n0 < 0 || m < 0)
+    return fail(PF_EINVAL, "null argument");
+  if (stride < h->ntot) return fail(PF_EINVAL, "trajectory stride below the field size");
+  for (int k = 0; k < 3; ++k)
+    if (!lam[k] || !work[k]) return fail(PF_EINVAL, "null field pointer");
+  const double* const lc[3] = {lam[0], lam[1], lam[2]};
+  const double* const wc[3] = {work[0], work[1], work[2]};
+  if (any_alias(lc, wc)) return fail(PF_EINVAL, "work may not alias lam");
+  if (m == 0) return PF_OK;
+  int nblk = 0;
+  int rc = adj_prepare(h, &nblk);
+  if (rc) return rc;
+  double* a[3] = {lam[0], lam[1], lam[2]};  // holds lam^{n0 + j + 1}
+  double* b[3] = {work[0], work[1], work[2]};
+  for (int64_t j = m - 1; j >= 0; --j) {
+    const double* u[3] = {traj_phi + j * stride, traj_cs + j * stride, traj_cl + j * stride};
+    const double* ac[3] = {a[0], a[1], a[2]};
+    if ((rc = adj_launch(h, n0 + j, u, ac, b, nblk, j < m - 1 ? 1 : 0))) return rc;
+    for (int k = 0; k < 3; ++k) std::swap(a[k], b[k]);
+  }
+  if (a[0] != lam[0]) {
+    const size_t bytes = (size_t)h->ntot * sizeof(double);
+    for (int k = 0; k < 3; ++k) PF_HIP(hipMemcpyAsync(lam[k], a[k], bytes, hipMemcpyDeviceToDevice, h->stream));
+  }
+  hipLaunchKernelGGL(pfadj::k_theta_final, dim3(1), dim3(256), 0, h->stream, h->c, h->d_theta_part, nblk, dtheta);
   PF_HIP(hipGetLastError());
   return PF_OK;
 }

@@ -20,7 +20,8 @@ PF_OK, PF_EINVAL, PF_EUNSTABLE_DT, PF_ENONFINITE, PF_ENEGCONC, PF_EDEVICE, PF_EN
 
 #: C symbols the header declares (checked by the CPU test of the library).
 EXPORTS = ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy", "pf_solute",
-           "pf_check", "pf_adjoint_step", "pf_kv_seed", "pf_destroy", "pf_strerror", "pf_last_error_detail")
+           "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed", "pf_destroy", "pf_strerror",
+           "pf_last_error_detail")
 
 
 class PFError(RuntimeError):
@@ -63,6 +64,7 @@ def lib() -> C.CDLL:
         L.pf_solute.argtypes = [vp, dp, dp, C.POINTER(i64)]
         L.pf_check.argtypes = [vp]
         L.pf_adjoint_step.argtypes = [vp, i64, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+        L.pf_adjoint_segment.argtypes = [vp, i64, i64, vp, vp, vp, i64, C.POINTER(vp), C.POINTER(vp), vp]
         L.pf_kv_seed.argtypes = [vp, dp, C.POINTER(vp)]
         L.pf_destroy.argtypes = [vp]
         L.pf_destroy.restype = None
@@ -71,7 +73,7 @@ def lib() -> C.CDLL:
         L.pf_last_error_detail.argtypes = []
         L.pf_last_error_detail.restype = C.c_char_p
         for name in ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy",
-                     "pf_solute", "pf_check", "pf_adjoint_step", "pf_kv_seed"):
+                     "pf_solute", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -202,6 +204,15 @@ def _ptr3(ts):
 def pf_adjoint_step(h: Handle, n: int, u_n, lam_np1, lam_n, dtheta):
     _check(lib().pf_adjoint_step(h.ptr, int(n), _ptr3(u_n), _ptr3(lam_np1), _ptr3(lam_n),
                                  C.c_void_p(_dev_ptr(dtheta))), "pf_adjoint_step")
+
+
+def pf_adjoint_segment(h: Handle, n0: int, m: int, traj, lam, work, dtheta):
+    """traj: three device tensors of shape (>= m, stride) (row j = state at step
+    n0 + j); lam: lam^{n0+m} in, lam^{n0} out; work: three scratch fields."""
+    stride = traj[0].shape[1]
+    _check(lib().pf_adjoint_segment(h.ptr, int(n0), int(m), C.c_void_p(_dev_ptr(traj[0])),
+                                    C.c_void_p(_dev_ptr(traj[1])), C.c_void_p(_dev_ptr(traj[2])), int(stride),
+                                    _ptr3(lam), _ptr3(work), C.c_void_p(_dev_ptr(dtheta))), "pf_adjoint_segment")
 
 
 def pf_kv_seed(h: Handle, dL_dk, lam):

@@ -152,3 +152,52 @@ def test_gradient_vs_finite_difference(torch_dev):
         fd[i] = (((kp - ktgt) ** 2).sum() - ((km - ktgt) ** 2).sum()).item() / (2 * h)
     for i in range(3):
         assert abs(g[i] - fd[i]) <= 1e-5 * max(abs(fd[i]), 1e-3 * np.abs(fd).max()), (i, g, fd)
+
+
+@pytest.mark.parametrize("dim,m", [(1, 7), (2, 6)])
+def test_segment_matches_steps(torch_dev, dim, m):
+    """pf_adjoint_segment over m replayed steps equals m pf_adjoint_step calls
+    to rounding order: the same kernels run, but the LDS scatter of the tiles
+    adds contributions in thread-arrival order, and dtheta carries the
+    per-block sums over the segment before reducing."""
+    from paper_2303_09671_amd import pf
+    torch = torch_dev
+    if dim == 1:
+        runs = [dict(N=300, V=0.3, dt=I.run_dt(0.3), z0=60 * I.DX), dict(N=520, V=0.05, dt=I.run_dt(0.05), z0=90 * I.DX)]
+        p = I.base_params(dim=1)
+        phi, cs, cl, offs = I.batch_fields(runs)
+        f = [_dev(torch, a) for a in (phi, cs, cl)]
+        h = pf.pf_create(p, *f, runs=runs, offsets=offs)
+        mask = torch.zeros(phi.size, dtype=torch.bool)  # run cells (not the alignment padding)
+        for r, o in zip(runs, offs):
+            mask[o:o + r["N"]] = True
+    else:
+        p, _, pert = I.config_2d(nx=48, nz=40)
+        p = dict(p, V=0.8, z0=12 * I.DX)
+        f = [_dev(torch, a.ravel()) for a in I.planar_front(2, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=3)]
+        h = pf.pf_create(p, *f)
+        mask = torch.ones(f[0].numel(), dtype=torch.bool)
+    print(f"case: segment vs steps dim={dim} m={m}", flush=True)
+    n0 = 29  # the 2D window shifts at step 31 -> 32 (V dt / dx = 1/31.25)
+    pf.pf_step(h, n0)
+    N = f[0].numel()
+    traj = [torch.empty((m + 1, N), dtype=torch.float64, device="cuda") for _ in range(3)]
+    pf.pf_step_traj(h, m, traj)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    lam_end = [torch.randn(N, generator=g, dtype=torch.float64).cuda() for _ in range(3)]
+    a = [x.clone() for x in lam_end]
+    b = [torch.empty_like(x) for x in lam_end]
+    th_steps = torch.zeros(3, dtype=torch.float64, device="cuda")
+    for j in reversed(range(m)):
+        pf.pf_adjoint_step(h, n0 + j, [traj[k][j] for k in range(3)], a, b, th_steps)
+        a, b = b, a
+    lam = [x.clone() for x in lam_end]
+    work = [torch.empty_like(x) for x in lam_end]
+    th_seg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    pf.pf_adjoint_segment(h, n0, m, traj, lam, work, th_seg)
+    torch.cuda.synchronize()
+    for k in range(3):
+        x, y = lam[k].cpu()[mask].numpy(), a[k].cpu()[mask].numpy()
+        assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(y)), k
+    ts, tg = th_steps.cpu().numpy(), th_seg.cpu().numpy()
+    assert np.all(np.abs(ts - tg) <= 1e-13 * np.abs(ts).max()), (ts, tg)
