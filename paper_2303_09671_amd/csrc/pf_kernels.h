@@ -252,75 +252,70 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
                             Fl);
   };
 
-  // Faces normal to in-plane axis K (0 = x, 1 = y) of plane gz into LDS.
-  auto inplane_faces = [&](auto axis, int gz) {
+  // The face normal to in-plane axis K (0 = x, 1 = y) of plane gz on the low
+  // side of cell (fa, fb) of the tile, into LDS.
+  auto face_item = [&](auto axis, int gz, int fa, int fb) {
     constexpr int K = decltype(axis)::value;
-    constexpr int NF = (K == 0) ? G::NFX : G::NFY;
     constexpr int RW = (K == 0) ? TX + 1 : TX;  // faces per row
     const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
     const int pt = (gz + 8) & 1;
     const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
     double* F0 = (K == 0) ? sfx[0] : sfy[0];
     double* F1 = (K == 0) ? sfx[1] : sfy[1];
-    // One face per thread, and the NF - NT faces left over go to one wave
-    // chosen per axis (x: wave 2, y: wave 3; the extra cells of the cell stage
-    // fall on waves 0 and 1), so the four waves carry equal work per plane.
-    constexpr int NW = G::NT / 64;
-    constexpr int E = NF - G::NT;
-    static_assert(E >= 0 && E <= 64, "tile shape: leftover faces must fit one wave");
-    constexpr int WE = (K + 2 < NW) ? K + 2 : NW - 1;
-    const int le = tid - 64 * WE;
-    const bool extra = (E > 0) && le >= 0 && le < E;
-    for (int it = 0; it < 2; ++it) {
-      if (it == 1 && !extra) break;
-      // item 0: the face on the low side of the own cell along K; item 1: one
-      // of the faces on the high side of the tile
-      const int fa = (it == 0) ? ox : ((K == 0) ? TX : le);
-      const int fb = (it == 0) ? oy : ((K == 0) ? le : TY);
-      const int f = fb * RW + fa;
-      // cell a = (ax, ay), cell b = a + e_K
-      const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
-      const int bx = fa, by = fb;
-      const int gface = (K == 0) ? x0 + fa : y0 + fb;
-      const int nk = (K == 0) ? nx : ny;
-      const int pk = (K == 0) ? c.px : c.py;
-      if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
-        F0[f] = 0.0;
-        F1[f] = 0.0;
-        continue;
-      }
-      const int ia = G::i2(ax, ay), ib = G::i2(bx, by);
-      const int ja = G::i1(ax, ay), jb = G::i1(bx, by);
-      double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
-      const double pa = su[s0][0][ia], pb = su[s0][0][ib];
-      const double ca = su[s0][1][ia], cb = su[s0][1][ib];
-      const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
-      gph[K] = pb - pa;  // dx-scaled face stage: plain differences and sums of them
-      gmu[K] = smu[m0][jb] - smu[m0][ja];
-      gcs[K] = cb - ca;
-      gcl[K] = lb_ - la_;
-      if (DIM == 3) {  // the other in-plane axis
-        constexpr int J = 1 - K;
-        constexpr int d2 = (J == 0) ? 1 : G::BX2;
-        constexpr int d1 = (J == 0) ? 1 : G::BX1;
-        gph[J] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
-        gmu[J] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
-        gcs[J] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
-        gcl[J] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
-      }
-      constexpr int kz = DIM - 1;  // transverse z
-      gph[kz] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
-      gmu[kz] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
-      gcs[kz] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
-      gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
-      const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
-      double Fs, Fl;
-      face_flux<DIM, K, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs,
-                             Fl);
-      F0[f] = Fs;
-      F1[f] = Fl;
+    const int f = fb * RW + fa;
+    // cell a = (ax, ay), cell b = a + e_K
+    const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
+    const int bx = fa, by = fb;
+    const int gface = (K == 0) ? x0 + fa : y0 + fb;
+    const int nk = (K == 0) ? nx : ny;
+    const int pk = (K == 0) ? c.px : c.py;
+    if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
+      F0[f] = 0.0;
+      F1[f] = 0.0;
+      return;
     }
+    const int ia = G::i2(ax, ay), ib = G::i2(bx, by);
+    const int ja = G::i1(ax, ay), jb = G::i1(bx, by);
+    double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
+    const double pa = su[s0][0][ia], pb = su[s0][0][ib];
+    const double ca = su[s0][1][ia], cb = su[s0][1][ib];
+    const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
+    gph[K] = pb - pa;  // dx-scaled face stage: plain differences and sums of them
+    gmu[K] = smu[m0][jb] - smu[m0][ja];
+    gcs[K] = cb - ca;
+    gcl[K] = lb_ - la_;
+    if (DIM == 3) {  // the other in-plane axis
+      constexpr int J = 1 - K;
+      constexpr int d2 = (J == 0) ? 1 : G::BX2;
+      constexpr int d1 = (J == 0) ? 1 : G::BX1;
+      gph[J] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
+      gmu[J] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
+      gcs[J] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
+      gcl[J] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
+    }
+    constexpr int kz = DIM - 1;  // transverse z
+    gph[kz] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
+    gmu[kz] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
+    gcs[kz] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
+    gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
+    const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
+    double Fs, Fl;
+    face_flux<DIM, K, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+    F0[f] = Fs;
+    F1[f] = Fl;
   };
+  // Face items: every thread takes the x and y faces on the low side of its own
+  // cell; the faces on the high side of the tile (TY of them in x, TX in y) go
+  // to wave 2 (x) and wave 3 (y), as the extra cells of the cell stage go to
+  // waves 0 and 1, so the four waves carry equal work per plane.
+  constexpr int NW = G::NT / 64;
+  constexpr int EX = G::NFX - G::NT, EY = G::NFY - G::NT;
+  static_assert(EX >= 0 && EX <= 64 && (DIM == 2 || (EY >= 0 && EY <= 64)),
+                "tile shape: leftover faces must fit one wave");
+  constexpr int WX = (2 < NW) ? 2 : NW - 1, WY = (3 < NW) ? 3 : NW - 1;
+  const int lex = tid - 64 * WX, ley = tid - 64 * WY;
+  const bool extra_x = (EX > 0) && lex >= 0 && lex < EX;
+  const bool extra_y = (DIM == 3) && (EY > 0) && ley >= 0 && ley < EY;
 
   // ---- prologue: ring = planes zb-1, zb, zb+1; rates of planes zb-1 and zb
   for (int g = zb - 1; g <= zb + 1; ++g) load_plane(g);
@@ -335,10 +330,13 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   for (int z = zb; z < ze; ++z) {
     cell_plane(z + 1, false, false);  // plane z+2 read from global memory
     __syncthreads();
-    inplane_faces(std::integral_constant<int, 0>{}, z);
-    if constexpr (DIM == 3) inplane_faces(std::integral_constant<int, 1>{}, z);
+    face_item(std::integral_constant<int, 0>{}, z, ox, oy);
+    if constexpr (DIM == 3) face_item(std::integral_constant<int, 1>{}, z, ox, oy);
     double FsU, FlU;
     zface(z, FsU, FlU);
+    if (extra_x) face_item(std::integral_constant<int, 0>{}, z, TX, lex);
+    if constexpr (DIM == 3)
+      if (extra_y) face_item(std::integral_constant<int, 1>{}, z, ley, TY);
     __syncthreads();
     if (own_valid) {
       const int s0 = slot3(z);
