@@ -1,0 +1,47 @@
+"""Adjoint-driven fit of theta = (A, M_phi, W) to a k(V) curve (Sec. V.C).
+
+Synthetic recovery: the target is the GPU forward's own k(V) at theta*; from
+a start theta0 away from it, Adam on the adjoint gradient must cut the loss by
+two orders of magnitude.  (k(V) does not pin theta uniquely -- the paper notes
+that several (A, b, W) give the same trapping -- so the test asks for the
+curve, not for theta*.)  Also: the gradient the fit uses points downhill (a
+small step along -grad lowers the loss).
+"""
+import numpy as np
+import pytest
+
+from paper_2303_09671_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload():
+    from paper_2303_09671_amd.adjoint import Workload
+    Vs = [0.05, 0.1, 0.2, 0.35, 0.6]
+    runs = [dict(N=512, V=V, dt=I.run_dt(V) * 0.5, z0=128 * I.DX) for V in Vs]
+    base = I.base_params(dim=1)
+    phi, cs, cl, offs = I.batch_fields(runs)
+    return Workload(params=base, fields0=(phi, cs, cl), nsteps=800, every=100, runs=runs, offsets=offs)
+
+
+def test_fit_recovers_curve():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_09671_amd.adjoint import forward_k
+    from paper_2303_09671_amd.fit import fit_theta, loss_and_grad
+    wl = _workload()
+    theta_star = np.array([1.05, 1.1, 0.95])
+    k_star = forward_k(wl, theta_star)[0].numpy()
+    theta0 = np.array([1.2, 1.0, 1.0])
+    print("case: fit 5 runs x 512 cells, 800 steps", flush=True)
+    L0, g0, _ = loss_and_grad(wl, k_star, theta0)
+    # a small step along -grad lowers the loss
+    step = 1e-3 / np.linalg.norm(g0)
+    L1 = loss_and_grad(wl, k_star, theta0 - step * g0)[0]
+    assert L1 < L0
+    res = fit_theta(wl, k_star, theta0, iters=15,
+                    log=lambda i, th, L: print(f"  it {i} theta {th} L {L:.3e}", flush=True))
+    print(f"  L0 {L0:.3e} -> {res.loss:.3e} at theta {res.theta} ({res.evaluations} evaluations)", flush=True)
+    assert all(b[1] <= a[1] for a, b in zip(res.history, res.history[1:]))  # monotone
+    assert res.loss <= 1e-2 * L0
