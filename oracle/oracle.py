@@ -10,6 +10,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
                        derivative w.r.t. the fields and theta = (A, M_phi, W);
 * :func:`energy`    -- discrete free energy (Eq. model1.1, dilute alloy Eq. dil_linear);
 * :func:`solute`    -- total solute, max c and its first index (Eq. model1, k_v of Sec. V.C);
+* :func:`front`     -- the phi = 1/2 front (topmost crossing per column) and its
+                       temperature (interface temperature of Sec. V.C);
 * :func:`pointwise` and :func:`phi_t` -- per-cell quantities for the pins.
 
 Parameters are a plain ``dict`` (see :data:`DEFAULTS`); fields are float64
@@ -69,6 +71,8 @@ def lib():
         L.orc_pointwise.restype = C.c_int
         L.orc_phi_t.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64, dp]
         L.orc_phi_t.restype = C.c_int
+        L.orc_front.argtypes = [C.POINTER(_Params), dp, C.c_long, C.c_int64, dp]
+        L.orc_front.restype = C.c_int
         if L.orc_params_size() != C.sizeof(_Params):
             raise RuntimeError("oracle parameter layout mismatch")
         _lib = L
@@ -157,6 +161,15 @@ def solute(p: dict, phi, cs, cl):
     tot, cm, am = C.c_double(), C.c_double(), C.c_long()
     lib().orc_solute(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), C.byref(tot), C.byref(cm), C.byref(am))
     return float(tot.value), float(cm.value), int(am.value)
+
+
+def front(p: dict, phi, n: int = 0, shift: int = 0) -> dict:
+    """The phi = 1/2 front: mean, min and max height over the columns that
+    cross, (mean - z0 - V n dt) / l_T and the number of crossing columns."""
+    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
+    out = np.zeros(5)
+    lib().orc_front(C.byref(_cparams(p)), _ptr(phi), int(n), int(shift), _ptr(out))
+    return dict(z=out[0], zmin=out[1], zmax=out[2], T=out[3], ncol=int(out[4]))
 
 
 def pointwise(p: dict, phi: float, cs: float, cl: float, cleq: float) -> dict:

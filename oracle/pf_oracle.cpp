@@ -42,6 +42,7 @@
 //
 // Build: g++ -O2 -std=c++17 -fno-fast-math -ffp-contract=off -shared -fPIC.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -517,6 +518,50 @@ int orc_solute(const OrcParams* P, const double* phi, const double* cs, const do
   if (total) *total = vol * sum;
   if (cmax) *cmax = mx;
   if (argmax) *argmax = am;
+  return 0;
+}
+
+// Solidification front (the phi = 1/2 level set) and its temperature, the
+// interface diagnostics of Sec. V.C (interface temperature T_I, read where
+// phi crosses one half).  In every growth-axis column (solid below, liquid
+// above) the front is the topmost crossing: the largest i with
+// phi_i >= 1/2 > phi_{i+1}, placed by linear interpolation between the two
+// cell centres, in lab coordinates z = (i + s + 1/2) dx + dx (phi_i - 1/2) /
+// (phi_i - phi_{i+1}) with s the window shift count.  Over the columns that
+// have a crossing: out = [mean z, min z, max z, (mean z - z0 - V t_n) / l_T,
+// number of such columns]; the fourth entry is (T_I - T_s) / dT0 of the
+// frozen temperature (Eq. ds1 with dT0 = G l_T, T_s the solidus of c_inf).
+// NaN for the first four when no column has a crossing.
+int orc_front(const OrcParams* P, const double* phi, long n, int64_t s_shift, double* out) {
+  Grid g = make_grid(*P);
+  const int gz = P->dim - 1;
+  const int nz = g.n[gz];
+  long ncol = 1;
+  for (int k = 0; k < gz; ++k) ncol *= g.n[k];
+  double sum = 0.0, zmin = INFINITY, zmax = -INFINITY;
+  long cnt = 0;
+  for (long col = 0; col < ncol; ++col) {
+    for (int i = nz - 2; i >= 0; --i) {
+      const double a = phi[col + ncol * (long)i], b = phi[col + ncol * (long)(i + 1)];
+      if (a >= 0.5 && b < 0.5) {
+        const double z = ((double)i + (double)s_shift + 0.5) * P->dx + P->dx * (a - 0.5) / (a - b);
+        sum += z;
+        zmin = std::min(zmin, z);
+        zmax = std::max(zmax, z);
+        ++cnt;
+        break;
+      }
+    }
+  }
+  if (cnt == 0) {
+    out[0] = out[1] = out[2] = out[3] = NAN;
+  } else {
+    out[0] = sum / (double)cnt;
+    out[1] = zmin;
+    out[2] = zmax;
+    out[3] = (out[0] - P->z0 - P->V * ((double)n * P->dt)) * P->inv_lT;
+  }
+  out[4] = (double)cnt;
   return 0;
 }
 
