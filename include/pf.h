@@ -120,6 +120,19 @@ int pf_energy(pf_handle* h, double* out);
  * partition coefficient of Sec. V.C is k = 1 / c_max.  Synchronous. */
 int pf_solute(pf_handle* h, double* total, double* cmax, int64_t* argmax);
 
+/* Solidification front and interface temperature (Sec. V.C reads the
+ * interface temperature where phi = 1/2): in every growth-axis column the
+ * topmost crossing -- the largest i with phi_i >= 1/2 > phi_{i+1} -- placed by
+ * linear interpolation between the two cell centres, in lab coordinates
+ * z = (i + s + 1/2) dx + dx (phi_i - 1/2) / (phi_i - phi_{i+1}) (s = window
+ * shift count of the current step).  Per run in batched mode (one column), else
+ * over the columns of the domain that cross: z_mean, z_min, z_max, the
+ * temperature T_front = (z_mean - z0 - V t_n) / l_T = (T_I - T_s) / dT0 of the
+ * frozen temperature field, and the number of crossing columns (0, with NaN
+ * heights and temperature, when nothing crosses).  HOST outputs (nbatch values,
+ * or 1); any pointer may be NULL.  Synchronous. */
+int pf_front(pf_handle* h, double* z_mean, double* z_min, double* z_max, double* T_front, int64_t* ncol);
+
 /* Error word of the fields since creation (or the last call of this
  * function): PF_OK, PF_ENONFINITE or PF_ENEGCONC.  Synchronous; clears it. */
 int pf_check(pf_handle* h);

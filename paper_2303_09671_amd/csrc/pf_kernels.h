@@ -820,4 +820,111 @@ __global__ void k_fill(double* __restrict__ a, double v, long long n) {
     a[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Solidification front (the interface diagnostic of Sec. V.C, where the
+// interface temperature is read at phi = 1/2): in every growth-axis column the
+// topmost crossing -- the largest i with phi_i >= 1/2 > phi_{i+1} -- placed by
+// linear interpolation between the two cell centres, in lab coordinates
+// z = (i + s + 1/2) dx + dx (phi_i - 1/2) / (phi_i - phi_{i+1}), s the window
+// shift count.  Results per run (1D) or per domain (2D/3D, over the columns that
+// cross): [mean z, min z, max z, (mean z - z0 - V t) / l_T, columns].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double front_z(int i, double a, double b, double s, double dx) {
+  return ((double)i + s + 0.5) * dx + dx * (a - 0.5) / (a - b);
+}
+
+// 2D/3D: one thread per column scans down from the top; NaN if no crossing.
+__global__ void k_front_cols(const double* __restrict__ phi, long long ncol, int nz, double s, double dx,
+                             double* __restrict__ zcol) {
+  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double z = __builtin_nan("");
+  double b = phi[col + ncol * (long long)(nz - 1)];
+  for (int i = nz - 2; i >= 0; --i) {
+    const double a = phi[col + ncol * (long long)i];
+    if (a >= 0.5 && b < 0.5) {
+      z = front_z(i, a, b, s, dx);
+      break;
+    }
+    b = a;
+  }
+  zcol[col] = z;
+}
+
+// One block: sums, extremes and count over the columns in a fixed order.
+constexpr int FRONT_THREADS = 256;
+__global__ void k_front_reduce(const double* __restrict__ zcol, long long ncol, double z_iso, double inv_lT,
+                               double* __restrict__ out) {
+  __shared__ double ssum[FRONT_THREADS], smin[FRONT_THREADS], smax[FRONT_THREADS], scnt[FRONT_THREADS];
+  const int t = threadIdx.x;
+  double sum = 0.0, mn = __builtin_inf(), mx = -__builtin_inf(), cnt = 0.0;
+  for (long long c = t; c < ncol; c += FRONT_THREADS) {
+    const double z = zcol[c];
+    if (z == z) {  // not NaN
+      sum += z;
+      mn = fmin(mn, z);
+      mx = fmax(mx, z);
+      cnt += 1.0;
+    }
+  }
+  ssum[t] = sum;
+  smin[t] = mn;
+  smax[t] = mx;
+  scnt[t] = cnt;
+  __syncthreads();
+  for (int w = FRONT_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      ssum[t] += ssum[t + w];
+      smin[t] = fmin(smin[t], smin[t + w]);
+      smax[t] = fmax(smax[t], smax[t + w]);
+      scnt[t] += scnt[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double nan = __builtin_nan("");
+    const double zm = (scnt[0] > 0.0) ? ssum[0] / scnt[0] : nan;
+    out[0] = zm;
+    out[1] = (scnt[0] > 0.0) ? smin[0] : nan;
+    out[2] = (scnt[0] > 0.0) ? smax[0] : nan;
+    out[3] = (zm - z_iso) * inv_lT;
+    out[4] = scnt[0];
+  }
+}
+
+// 1D runs: one block per run; the largest crossing index by a block maximum.
+__global__ void k_front_runs(Const c, RunTab rt, const double* __restrict__ phi, long long n,
+                             double* __restrict__ out) {
+  __shared__ int sbest[FRONT_THREADS];
+  const int r = blockIdx.x, t = threadIdx.x;
+  const int N = rt.n[r];
+  const long long off = rt.off[r];
+  int best = -1;
+  for (int i = t; i + 1 < N; i += FRONT_THREADS)
+    if (phi[off + i] >= 0.5 && phi[off + i + 1] < 0.5) best = i;  // increasing i: the last hit is the largest
+  sbest[t] = best;
+  __syncthreads();
+  for (int w = FRONT_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) sbest[t] = max(sbest[t], sbest[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    double* o = out + 5 * r;
+    const int i = sbest[0];
+    if (i < 0) {
+      const double nan = __builtin_nan("");
+      o[0] = o[1] = o[2] = o[3] = nan;
+      o[4] = 0.0;
+    } else {
+      const double V = rt.V[r], dt = rt.dt[r];
+      const double tn = (double)n * dt;
+      const double s = floor(V * tn / c.dx);
+      const double z = front_z(i, phi[off + i], phi[off + i + 1], s, c.dx);
+      o[0] = o[1] = o[2] = z;
+      o[3] = (z - rt.z0[r] - V * tn) * c.inv_lT;
+      o[4] = 1.0;
+    }
+  }
+}
+
 }  // namespace pfk

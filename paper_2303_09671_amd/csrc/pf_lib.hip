@@ -78,6 +78,8 @@ struct pf_handle {
   pfadj::Tile1* d_tiles = nullptr;   // adjoint: (run, tile) table of 1D runs
   int ntiles = 0;
   int* d_err = nullptr;
+  double* d_front = nullptr;      // front diagnostic: 5 values per run
+  double* d_front_col = nullptr;  // 2D/3D: crossing height per column
   int zchunk = 32;  // z planes per workgroup of the streaming kernel
   long long n = 0;  // step counter
 
@@ -543,6 +545,41 @@ int pf_solute(pf_handle* h, double* total, double* cmax, int64_t* argmax) {
   return PF_OK;
 }
 
+int pf_front(pf_handle* h, double* z_mean, double* z_min, double* z_max, double* T_front, int64_t* ncol) {
+  if (!h) return fail(PF_EINVAL, "null handle");
+  int rc;
+  if (!h->d_front && (rc = dalloc(&h->d_front, (size_t)5 * h->nrun))) return rc;
+  const pfk::Const& c = h->c;
+  if (h->batched) {
+    hipLaunchKernelGGL(pfk::k_front_runs, dim3(h->nrun), dim3(pfk::FRONT_THREADS), 0, h->stream, c, h->runtab(),
+                       h->f[0], (long long)h->n, h->d_front);
+    PF_HIP(hipGetLastError());
+  } else {
+    const int nz = c.nz;  // 2D and 3D (1D runs take the batched path)
+    const long long cols = h->ntot / nz;
+    if (!h->d_front_col && (rc = dalloc(&h->d_front_col, (size_t)cols))) return rc;
+    const double tn = (double)h->n * c.dt;
+    const double s = std::floor(c.V * tn / c.dx);
+    hipLaunchKernelGGL(pfk::k_front_cols, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, h->stream, h->f[0],
+                       cols, nz, s, c.dx, h->d_front_col);
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(pfk::k_front_reduce, dim3(1), dim3(pfk::FRONT_THREADS), 0, h->stream, h->d_front_col, cols,
+                       c.z0 + c.V * tn, c.inv_lT, h->d_front);
+    PF_HIP(hipGetLastError());
+  }
+  std::vector<double> r((size_t)5 * h->nrun);
+  PF_HIP(hipMemcpyAsync(r.data(), h->d_front, sizeof(double) * r.size(), hipMemcpyDeviceToHost, h->stream));
+  PF_HIP(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < h->nrun; ++i) {
+    if (z_mean) z_mean[i] = r[5 * i];
+    if (z_min) z_min[i] = r[5 * i + 1];
+    if (z_max) z_max[i] = r[5 * i + 2];
+    if (T_front) T_front[i] = r[5 * i + 3];
+    if (ncol) ncol[i] = (int64_t)r[5 * i + 4];
+  }
+  return PF_OK;
+}
+
 int pf_check(pf_handle* h) {
   if (!h) return fail(PF_EINVAL, "null handle");
   return read_err(h, true);
@@ -693,6 +730,8 @@ void pf_destroy(pf_handle* h) {
   (void)hipFree(h->d_theta_part);
   (void)hipFree(h->d_tiles);
   (void)hipFree(h->d_err);
+  (void)hipFree(h->d_front);
+  (void)hipFree(h->d_front_col);
   delete h;
 }
 

@@ -20,7 +20,7 @@ PF_OK, PF_EINVAL, PF_EUNSTABLE_DT, PF_ENONFINITE, PF_ENEGCONC, PF_EDEVICE, PF_EN
 
 #: C symbols the header declares (checked by the CPU test of the library).
 EXPORTS = ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy", "pf_solute",
-           "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed", "pf_destroy", "pf_strerror",
+           "pf_front", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed", "pf_destroy", "pf_strerror",
            "pf_last_error_detail")
 
 
@@ -62,6 +62,7 @@ def lib() -> C.CDLL:
         L.pf_set_step.argtypes = [vp, i64]
         L.pf_energy.argtypes = [vp, dp]
         L.pf_solute.argtypes = [vp, dp, dp, C.POINTER(i64)]
+        L.pf_front.argtypes = [vp, dp, dp, dp, dp, C.POINTER(i64)]
         L.pf_check.argtypes = [vp]
         L.pf_adjoint_step.argtypes = [vp, i64, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
         L.pf_adjoint_segment.argtypes = [vp, i64, i64, vp, vp, vp, i64, C.POINTER(vp), C.POINTER(vp), vp]
@@ -73,7 +74,7 @@ def lib() -> C.CDLL:
         L.pf_last_error_detail.argtypes = []
         L.pf_last_error_detail.restype = C.c_char_p
         for name in ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy",
-                     "pf_solute", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed"):
+                     "pf_solute", "pf_front", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -187,6 +188,16 @@ def pf_solute(h: Handle):
     _check(lib().pf_solute(h.ptr, tot.ctypes.data_as(C.POINTER(C.c_double)), cm.ctypes.data_as(C.POINTER(C.c_double)),
                            am.ctypes.data_as(C.POINTER(C.c_int64))), "pf_solute")
     return tot, cm, am
+
+
+def pf_front(h: Handle) -> dict:
+    """The phi = 1/2 front: arrays (one entry per run) z, zmin, zmax, T, ncol."""
+    z, zmin, zmax, T = (np.zeros(h.nrun) for _ in range(4))
+    nc = np.zeros(h.nrun, dtype=np.int64)
+    dpp = C.POINTER(C.c_double)
+    _check(lib().pf_front(h.ptr, z.ctypes.data_as(dpp), zmin.ctypes.data_as(dpp), zmax.ctypes.data_as(dpp),
+                          T.ctypes.data_as(dpp), nc.ctypes.data_as(C.POINTER(C.c_int64))), "pf_front")
+    return dict(z=z, zmin=zmin, zmax=zmax, T=T, ncol=nc)
 
 
 def pf_check(h: Handle) -> int:
