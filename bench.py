@@ -16,7 +16,8 @@ before timing starts.  Prints ONE JSON line:
                 256^3 grid), single thread;
 * extra      -- the other workloads of the hot path: 2D 1024^2, the 1D front,
                 the batched 256-run k(V) sweep against 256 sequential launches,
-                and (when built) the adjoint/forward step-time ratio.
+                the adjoint/forward step-time ratio, and the solute-band run
+                (interface temperature and velocity from the phi = 1/2 front).
 """
 from __future__ import annotations
 
@@ -133,6 +134,30 @@ def bench_adjoint(torch, nsteps=2000):
     return res
 
 
+def bench_bands(torch, pf, every=2000):
+    """The solute-band workload (Si-9%As, G = 1.4e6 K/m, v_p = 0.3 m/s): one
+    long 1D run with the phi = 1/2 front read every ``every`` steps; the
+    interface temperature and velocity of its second half."""
+    from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd.front import front_series
+    p, steps = I.config_bands()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    t = [dev(torch, a) for a in f]
+    h = pf.pf_create(p, *t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ser = front_series(h, steps, every, p["dt"])
+    torch.cuda.synchronize()
+    d = time.perf_counter() - t0
+    half = len(ser["n"]) // 2
+    T, v = ser["T"][half:, 0], ser["v"][half:, 0]
+    _, cm, _ = pf.pf_solute(h)
+    return dict(cells=p["n"][0], steps=steps, seconds=d, cell_updates_per_s=p["n"][0] * steps / d,
+                front_every=every, z_final=float(ser["z"][-1, 0]), k=float(1.0 / cm[0]),
+                T_I_second_half=[float(T.min()), float(T.mean()), float(T.max())],
+                v_I_second_half=[float(v.min()), float(v.mean()), float(v.max())], V_pull=p["V"])
+
+
 def cpu_baseline(p, pert):
     from oracle import oracle as O
     from paper_2303_09671_amd import inputs as I
@@ -231,6 +256,7 @@ def main():
         extra["1d_1024_20000_steps"] = dict(seconds=d1, cell_updates_per_s=1024 * steps1 / d1, k=float(1.0 / cm[0]))
         extra["batch_256_runs"] = bench_batch(torch, pf, 2000)
         extra["adjoint"] = bench_adjoint(torch)
+        extra["bands_1d_2048"] = bench_bands(torch, pf)
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

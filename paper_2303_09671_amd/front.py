@@ -1,0 +1,48 @@
+"""Time series of the solidification front (pf_front) while stepping.
+
+The interface temperature and velocity of Sec. V.C / Figs. 8-9 are read from
+the phi = 1/2 front: every ``every`` steps the library reports the front
+height z (lab frame) and (T_I - T_s)/dT0; the interface velocity is the
+centred difference of z in time.  All arithmetic on the fields runs in the HIP
+library; this module only records the scalars.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import pf
+
+
+def front_series(h: pf.Handle, nsteps: int, every: int, dt):
+    """Step ``h`` by ``nsteps``, reading the front every ``every`` steps (and at
+    the start).  ``dt``: the time step (a scalar, or one per run).  Returns a
+    dict of arrays shaped (samples, runs): n, t, z, T, and v (dz/dt, centred
+    inside, one-sided at the ends; NaN where the front is missing)."""
+    n0 = pf.pf_get_step(h)
+    ns, zs, Ts = [], [], []
+    done = 0
+    while True:
+        fr = pf.pf_front(h)
+        ns.append(n0 + done)
+        zs.append(fr["z"])
+        Ts.append(fr["T"])
+        if done >= nsteps:
+            break
+        m = min(every, nsteps - done)
+        pf.pf_step(h, m)
+        done += m
+    n = np.asarray(ns, dtype=np.int64)
+    t = n[:, None] * np.broadcast_to(np.asarray(dt, dtype=np.float64), (h.nrun,))[None, :]
+    z = np.asarray(zs)
+    T = np.asarray(Ts)
+    v = np.gradient(z, t[:, 0], axis=0) if len(n) > 1 and np.all(t[:, 0] == t[:, -1]) else _grad_runs(z, t)
+    return dict(n=n, t=t, z=z, T=T, v=v)
+
+
+def _grad_runs(z, t):
+    v = np.full_like(z, np.nan)
+    if len(z) < 2:
+        return v
+    for r in range(z.shape[1]):
+        v[:, r] = np.gradient(z[:, r], t[:, r])
+    return v

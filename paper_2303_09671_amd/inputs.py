@@ -93,6 +93,22 @@ def config_3d(n: int = 256, steps: int = 2000, seed: int = 2, amp: float = 1e-3)
     return p, steps, dict(amp=amp, seed=seed)
 
 
+def config_bands(N: int = 2048, steps: int = 200000):
+    """Long 1D run of the solute-band study (Figs. 8-9): Si-9%As (k_e = 0.3,
+    liquidus slope -4 K/%, c_inf = 9 %, so the freezing range is dT0 = 84 K;
+    D_l = 1.5e-8 m^2/s) with W = 13.5 nm, G = 1.4e6 K/m (l_T = dT0 / G =
+    6e-5 m = 4444 W), v_p = 0.3 m/s (V = v_p W / D_l = 0.27) and D_s/D_l = 1e-3;
+    b = 1e-3 and lambda0 = I k_e / (1 - k_e)^2 (W/d0 = 1), A = 1.2 (the
+    explicit scheme is stable there; A = 2 of the paper's fit is not);
+    dt = 0.2 dx^2, front at N/4, no-flux ends, 200000 steps (about 1.6
+    thermal times l_T / V)."""
+    I0 = 1.0 / (3.0 * math.sqrt(2.0))
+    ke = 0.3
+    p = base_params(dim=1, n=(N, 1, 1), V=0.27, dt=0.2 * DX * DX, z0=(N // 4) * DX)
+    p.update(ke=ke, Ds=1e-3, b=1e-3, A=1.2, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=1.0 / 4444.0)
+    return p, steps
+
+
 def run_dt(V: float, dx: float = DX, alpha: float = 1.0, W: float = 1.0) -> float:
     """Per-run time step from the run's stability limits (diffusion, window
     advection, phi relaxation)."""

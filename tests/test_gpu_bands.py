@@ -1,0 +1,36 @@
+"""The solute-band workload (Figs. 8-9 parameters, Si-9%As at G = 1.4e6 K/m,
+v_p = 0.3 m/s): a prefix of the long 1D run against the oracle at the usual
+1e-10, with the front diagnostic on the same state; and the front time series
+helper reading a front that follows the pulling speed."""
+import numpy as np
+import pytest
+
+from paper_2303_09671_amd import inputs as I
+from tests.helpers import assert_parity, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+def test_bands_prefix(oracle):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_09671_amd import pf
+    from paper_2303_09671_amd.front import front_series
+    p, _ = I.config_bands()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f]
+    h = pf.pf_create(p, *t)
+    steps = 3000
+    print(f"case: bands prefix {steps} steps", flush=True)
+    ser = front_series(h, steps, 500, p["dt"])
+    g = [x.cpu().numpy() for x in t]
+    po = oracle_params(oracle, p)
+    ref = oracle.step(po, *f, steps)
+    assert_parity(g, ref[:3], what="bands prefix")
+    fr = oracle.front(po, g[0], n=steps, shift=ref[3])
+    assert abs(ser["z"][-1, 0] - fr["z"]) <= 1e-12 * abs(fr["z"])
+    assert abs(ser["T"][-1, 0] - fr["T"]) <= 1e-10
+    # the front advances with the pulling speed to within 20 % over the prefix
+    v = (ser["z"][-1, 0] - ser["z"][1, 0]) / (ser["t"][-1, 0] - ser["t"][1, 0])
+    assert abs(v - p["V"]) <= 0.2 * p["V"], v
