@@ -94,3 +94,47 @@ def test_zero_steps(torch_dev):
     assert pf.pf_get_step(h) == 17
     for x, a in zip(t, f):
         assert np.array_equal(x.cpu().numpy(), a)
+
+
+def test_api_errors(torch_dev):
+    """Invalid calls are rejected with PF_EINVAL before any launch."""
+    from paper_2303_09671_amd import pf
+    torch = torch_dev
+    p, _, pert = I.config_3d(n=8)
+    p = dict(p, n=(16, 8, 20))
+    f = [_dev(torch, a) for a in I.planar_front(3, p["n"], p["dx"], p["z0"], p["ke"])]
+    h = pf.pf_create(p, *f)
+    N = f[0].numel()
+    lam = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(3)]
+    out = [torch.zeros_like(x) for x in lam]
+    dth = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(pf.PFError) as e:  # no 3D adjoint
+        pf.pf_adjoint_step(h, 0, f, lam, out, dth)
+    assert e.value.code == pf.PF_EINVAL
+    with pytest.raises(pf.PFError) as e:  # trajectory rows shorter than the field
+        pf.pf_step_traj(h, 2, [torch.zeros((3, N - 1), dtype=torch.float64, device="cuda") for _ in range(3)])
+    assert e.value.code == pf.PF_EINVAL
+    # 2D adjoint: output aliasing the input cotangent, and a periodic axis narrower than a tile box
+    p2, _, _ = I.config_2d(nx=40, nz=30)
+    f2 = [_dev(torch, a.ravel()) for a in I.planar_front(2, p2["n"], p2["dx"], p2["z0"], p2["ke"])]
+    h2 = pf.pf_create(p2, *f2)
+    l2 = [torch.zeros_like(x) for x in f2]
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_adjoint_step(h2, 0, f2, l2, [l2[1], torch.zeros_like(l2[0]), torch.zeros_like(l2[0])], dth)
+    assert e.value.code == pf.PF_EINVAL
+    p3, _, _ = I.config_2d(nx=12, nz=30)
+    f3 = [_dev(torch, a.ravel()) for a in I.planar_front(2, p3["n"], p3["dx"], p3["z0"], p3["ke"])]
+    h3 = pf.pf_create(p3, *f3)
+    l3 = [torch.zeros_like(x) for x in f3]
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_adjoint_step(h3, 0, f3, l3, [torch.zeros_like(x) for x in l3], dth)
+    assert e.value.code == pf.PF_EINVAL
+    # a 1D run longer than the persistent kernel holds, and a bad grid
+    pl, _ = I.config_1d(N=9000)
+    fl = [_dev(torch, a) for a in I.planar_front(1, pl["n"], pl["dx"], pl["z0"], pl["ke"])]
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(pl, *fl)
+    assert e.value.code == pf.PF_EINVAL
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(dict(p, n=(16, 8, 2)), *f)
+    assert e.value.code == pf.PF_EINVAL
