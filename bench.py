@@ -115,7 +115,9 @@ def bench_batch(torch, pf, steps):
 def bench_adjoint(torch, nsteps=2000):
     """Adjoint/forward step-time ratio on the adjoint fit workloads (64 1D runs
     N = 2048; 2D 512^2), over nsteps with checkpoints every 100 steps: forward
-    pass with checkpoints vs backward (segment replay + adjoint steps)."""
+    pass with checkpoints vs backward (segment replay + adjoint steps), with the
+    replays overlapped on a second stream (ratio) and one after the other
+    (ratio_serial)."""
     from paper_2303_09671_amd import inputs as I
     from paper_2303_09671_amd.adjoint import Workload, adjoint_only_seconds, forward_k
     one_d, two_d, _, _ = I.adjoint_workloads()
@@ -130,7 +132,9 @@ def bench_adjoint(torch, nsteps=2000):
         torch.cuda.synchronize()
         tf = time.perf_counter() - t0
         tb = adjoint_only_seconds(wl, theta)
-        res[name] = dict(steps=nsteps, forward_s=tf, backward_s=tb, ratio=tb / tf)
+        ts = adjoint_only_seconds(wl, theta, overlap=False)
+        res[name] = dict(steps=nsteps, forward_s=tf, backward_s=tb, ratio=tb / tf,
+                         backward_serial_s=ts, ratio_serial=ts / tf)
     return res
 
 

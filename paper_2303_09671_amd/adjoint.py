@@ -8,8 +8,10 @@ Sec. V.C: 1 / max c with c = p c_s + (1-p) c_l).  Its backward seeds the
 adjoint at the final state with dL/dk (pf_kv_seed), then for each checkpoint
 segment in reverse replays the segment's states (pf_step_traj) and takes the
 adjoint steps backwards over them in one call (pf_adjoint_segment),
-accumulating dL/dtheta on the device.  Torch supplies device memory and the
-stream only.
+accumulating dL/dtheta on the device.  The replay of the next (earlier) segment
+runs on a second stream, with its own handle and fields, while the adjoint of
+the current one runs on the handle's stream (two trajectory buffers, ordered by
+events).  Torch supplies device memory and the streams only.
 """
 from __future__ import annotations
 
@@ -68,42 +70,74 @@ def forward_k(workload: Workload, theta, checkpoints: bool = False):
 class PartitionCoefficient(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta: torch.Tensor, workload: Workload):
-        k, h, fields, ck = forward_k(workload, theta.detach().cpu().numpy(), checkpoints=True)
+        th = theta.detach().cpu().numpy()
+        k, h, fields, ck = forward_k(workload, th, checkpoints=True)
         ctx.workload = workload
-        ctx.state = (h, fields, ck)
+        ctx.state = (h, fields, ck, th)
         return k
 
     @staticmethod
     def backward(ctx, grad_k):
-        h, fields, ck = ctx.state
-        wl = ctx.workload
+        h, fields, ck, th = ctx.state
         lam = [torch.empty_like(fields[0]) for _ in range(3)]
         pf.pf_kv_seed(h, grad_k.detach().cpu().numpy().astype(np.float64), lam)
-        dtheta = _backward_segments(h, wl, fields, ck, lam)
+        dtheta = _backward_segments(h, ctx.workload, th, fields, ck, lam)
         ctx.state = None
         return dtheta.cpu(), None
 
 
-def _backward_segments(h, wl: Workload, fields, ck, lam):
+def _backward_segments(h, wl: Workload, theta, fields, ck, lam, overlap: bool = True):
     """Replay each checkpoint segment in reverse and take its adjoint steps;
-    lam holds the cotangent of the final state on entry.  Returns dL/dtheta."""
+    lam holds the cotangent of the final state on entry.  Returns dL/dtheta.
+    With ``overlap`` the replays run on a second stream one segment ahead."""
+    main = h.stream
+    side = torch.cuda.Stream(device=fields[0].device) if overlap else main
     nfield = fields[0].numel()
-    work = [torch.empty_like(fields[0]) for _ in range(3)]
-    dtheta = torch.zeros(3, dtype=torch.float64, device=fields[0].device)
     K = wl.every
-    traj = [torch.empty((K + 1, nfield), dtype=torch.float64, device=fields[0].device) for _ in range(3)]
-    for s in reversed(range(len(ck))):
+    nseg = len(ck)
+    with torch.cuda.stream(main):
+        work = [torch.empty_like(fields[0]) for _ in range(3)]
+        dtheta = torch.zeros(3, dtype=torch.float64, device=fields[0].device)
+        trajs = [[torch.empty((K + 1, nfield), dtype=torch.float64, device=fields[0].device) for _ in range(3)]
+                 for _ in range(2)]
+        rep_fields = [torch.empty_like(f) for f in fields]
+    side.wait_stream(main)  # checkpoints, buffers and the seed are ready
+    h_rep = pf.pf_create(_params_with(wl, theta), *rep_fields, stream=side, runs=wl.runs, offsets=wl.offsets)
+    free = [None, None]  # per buffer: event after the adjoint that last read it
+
+    def replay(s):
         n0 = s * K
         m = min(K, wl.nsteps - n0)
-        for f, c in zip(fields, ck[s]):
-            f.copy_(c)
-        pf.pf_set_step(h, n0)
-        pf.pf_step_traj(h, m, traj)
-        pf.pf_adjoint_segment(h, n0, m, traj, lam, work, dtheta)
+        buf = trajs[s % 2]
+        with torch.cuda.stream(side):
+            if free[s % 2] is not None:
+                side.wait_event(free[s % 2])
+            for f, c in zip(rep_fields, ck[s]):
+                f.copy_(c)
+            pf.pf_set_step(h_rep, n0)
+            pf.pf_step_traj(h_rep, m, buf)
+            ev = torch.cuda.Event()
+            ev.record(side)
+        return ev
+
+    ready = replay(nseg - 1)
+    for s in reversed(range(nseg)):
+        n0 = s * K
+        m = min(K, wl.nsteps - n0)
+        main.wait_event(ready)
+        if s > 0:
+            ready = replay(s - 1)  # overlaps the adjoint of segment s
+        pf.pf_adjoint_segment(h, n0, m, trajs[s % 2], lam, work, dtheta)
+        ev = torch.cuda.Event()
+        ev.record(main)
+        free[s % 2] = ev
+    main.wait_stream(side)
+    main.synchronize()  # the buffers above are released on return
+    pf.pf_destroy(h_rep)
     return dtheta
 
 
-def adjoint_only_seconds(workload: Workload, theta, nsteps: int | None = None) -> float:
+def adjoint_only_seconds(workload: Workload, theta, overlap: bool = True) -> float:
     """Wall time of the backward pass alone (replay + adjoint) for timing."""
     import time
     k, h, fields, ck = forward_k(workload, theta, checkpoints=True)
@@ -111,6 +145,6 @@ def adjoint_only_seconds(workload: Workload, theta, nsteps: int | None = None) -
     pf.pf_kv_seed(h, np.ones(workload.nrun), lam)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _backward_segments(h, workload, fields, ck, lam)
+    _backward_segments(h, workload, theta, fields, ck, lam, overlap=overlap)
     torch.cuda.synchronize()
     return time.perf_counter() - t0

@@ -95,11 +95,12 @@ def _dev_ptr(t) -> int:
 class Handle:
     """An open pf_handle plus the objects whose memory it references."""
 
-    def __init__(self, ptr: int, fields, params: dict, nrun: int, keep):
+    def __init__(self, ptr: int, fields, params: dict, nrun: int, keep, stream=None):
         self.ptr = C.c_void_p(ptr)
         self.fields = fields
         self.params = params
         self.nrun = nrun
+        self.stream = stream  # the torch stream every call of this handle is ordered on
         self._keep = keep
 
     def __del__(self):
@@ -150,7 +151,8 @@ def pf_create(params: dict, phi, cs, cl, stream=None, runs=None, offsets=None) -
     rc = lib().pf_create(C.byref(s), C.c_void_p(_dev_ptr(phi)), C.c_void_p(_dev_ptr(cs)), C.c_void_p(_dev_ptr(cl)),
                          C.c_void_p(stream.cuda_stream), C.byref(out))
     _check(rc, "pf_create")
-    return Handle(out.value, (phi, cs, cl), dict(params), len(runs) if runs is not None else 1, keep + [stream])
+    return Handle(out.value, (phi, cs, cl), dict(params), len(runs) if runs is not None else 1, keep + [stream],
+                  stream)
 
 
 def pf_step(h: Handle, nsteps: int):
