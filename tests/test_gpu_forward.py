@@ -146,6 +146,34 @@ def test_interpolation_variants(torch_dev, oracle, dim, quintic, ap):
     assert_parity(g, ref[:3], what=f"{dim}D quintic={quintic} ap={ap}")
 
 
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_source_A_equals_one(torch_dev, oracle, dim):
+    """A = 1 (the special case without anti-trapping: every (1 - A) term of the
+    drive, the prefactor and the fluxes vanishes) through each step kernel.
+    A < 1 - k_e drives the ghost c_s negative in this scheme (both sides go
+    non-finite), so it is not a parity case."""
+    if dim == 1:
+        p, _ = I.config_1d(N=700)
+        p = dict(p, z0=175 * I.DX)
+        f = list(I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"]))
+        steps = 1500
+    elif dim == 2:
+        p, _, pert = I.config_2d(nx=70, nz=48)
+        p = dict(p, V=0.5, z0=14 * I.DX)
+        f = [a.ravel() for a in I.planar_front(2, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+        steps = 200
+    else:
+        p, _, pert = I.config_3d(n=8)
+        p = dict(p, n=(36, 10, 40), V=0.6, z0=14 * I.DX)
+        f = [a.ravel() for a in I.planar_front(3, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+        steps = 80
+    p = dict(p, A=1.0)
+    print(f"case: A = 1, {dim}D, {steps} steps", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert_parity(g, ref[:3], what=f"A=1 {dim}D")
+
+
 @pytest.mark.parametrize("which", ["2d", "3d"])
 def test_full_size_one_step(torch_dev, oracle, which):
     """Workload sizes as configured (2D 1024^2, 3D 256^3), same launch
