@@ -40,9 +40,15 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_09671_amd", "csrc", f) for f in
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code (comments and layout stripped), so a
+    traffic record stays valid exactly while the compiled kernel is the same."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        src = open(f).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

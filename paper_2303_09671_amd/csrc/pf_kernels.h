@@ -34,14 +34,15 @@ __device__ __forceinline__ int map_axis(int g, int n, int periodic) {
 
 // ---------------------------------------------------------------------------
 // Fused step for 2D and 3D: each workgroup owns a TX x TY column tile of the
-// transverse plane(s) and streams through a range of z planes.  A 4-plane ring
-// of (phi, c_s, c_l) with an in-plane halo of 2 lives in LDS; phi_t and mu_bar
-// of each plane are computed once on the tile plus an in-plane halo of 1 and
-// kept in 2- and 3-plane rings; x/y face fluxes go through LDS and the z-face
-// flux below a cell stays in a register for the next plane.  One HBM read and
-// one HBM write of the three fields per cell and step (plus halo re-reads that
-// hit L2).  With a window shift the updated plane z is stored at z-1 and the
-// fresh liquid layer at the top.
+// transverse plane(s) and streams through a range of z planes.  A 3-plane ring
+// (z-1, z, z+1) of (phi, c_s, c_l) with an in-plane halo of 2 lives in LDS;
+// phi_t and mu_bar of each plane are computed once on the tile plus an in-plane
+// halo of 1 (the plane z+2 they need above comes straight from global memory)
+// and kept in 2- and 3-plane rings; x/y face fluxes go through LDS and the
+// z-face flux below a cell stays in a register for the next plane.  One HBM read
+// and one HBM write of the three fields per cell and step, plus halo re-reads
+// (mostly L2 hits).  With a window shift the updated plane z is stored at z-1
+// and the fresh liquid layer at the top.
 // ---------------------------------------------------------------------------
 template <int DIM, int TX, int TY>
 struct StreamGeom {
