@@ -70,11 +70,11 @@ typedef struct pf_params {
   double inv_lT;        /* 1 / thermal length l_T = dT0 / G (0: isothermal at T_s)  */
   double V;             /* pulling speed (single domain)                            */
   double z0;            /* initial front height (lab frame)                         */
-  double eps_grad;      /* |grad phi|^2 gate of the normal projection (e.g. 1e-20)  */
+  double eps_grad;      /* eps of 1/|grad phi|^2 ~ G / (G^2 + eps^2), G = |grad phi|^2 */
   /* batched 1D runs: nbatch > 0 and dim == 1.  Host arrays, copied by pf_create. */
   int32_t nbatch;
   int32_t pad_;
-  const int32_t* run_n;    /* cells of run r (8 <= run_n[r] <= 8192)               */
+  const int32_t* run_n;    /* cells of run r (3 <= run_n[r] <= 8192)               */
   const int64_t* run_off;  /* first cell of run r in the field arrays              */
   const double* run_V;     /* pulling speed of run r                               */
   const double* run_dt;    /* time step of run r                                   */
