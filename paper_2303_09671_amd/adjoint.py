@@ -86,6 +86,31 @@ class PartitionCoefficient(torch.autograd.Function):
         return dtheta.cpu(), None
 
 
+class FinalState(torch.autograd.Function):
+    """The fields (phi, c_s, c_l) after ``workload.nsteps`` steps as a
+    differentiable function of theta, for losses on the interface profile or
+    the concentration fields: the backward receives dL/du at the final state
+    (computed by torch from any loss on the returned tensors) and runs the same
+    checkpointed adjoint as PartitionCoefficient."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, workload: Workload):
+        th = theta.detach().cpu().numpy()
+        _, h, fields, ck = forward_k(workload, th, checkpoints=True)
+        ctx.workload = workload
+        ctx.state = (h, fields, ck, th)
+        return tuple(f.clone() for f in fields)
+
+    @staticmethod
+    def backward(ctx, g_phi, g_cs, g_cl):
+        h, fields, ck, th = ctx.state
+        lam = [torch.zeros_like(fields[0]) if g is None else g.detach().clone().contiguous()
+               for g in (g_phi, g_cs, g_cl)]
+        dtheta = _backward_segments(h, ctx.workload, th, fields, ck, lam)
+        ctx.state = None
+        return dtheta.cpu(), None
+
+
 def _backward_segments(h, wl: Workload, theta, fields, ck, lam, overlap: bool = True):
     """Replay each checkpoint segment in reverse and take its adjoint steps;
     lam holds the cotangent of the final state on entry.  Returns dL/dtheta.

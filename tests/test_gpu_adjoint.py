@@ -201,3 +201,65 @@ def test_segment_matches_steps(torch_dev, dim, m):
         assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(y)), k
     ts, tg = th_steps.cpu().numpy(), th_seg.cpu().numpy()
     assert np.all(np.abs(ts - tg) <= 1e-13 * np.abs(ts).max()), (ts, tg)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_profile_loss_gradient_vs_finite_difference(torch_dev, dim):
+    """An interface-profile loss on the final fields, L = sum w (phi - phi*)^2 +
+    sum w (c - c*)^2 with the mixture concentration c = p c_s + (1 - p) c_l
+    (Eq. model1) and targets from a run at another theta, differentiated
+    through FinalState (torch supplies dL/du, the library's adjoint the rest),
+    against central differences with h = 1e-6.  (A loss on a phase
+    concentration alone would also weigh its ghost values -- c_l deep in the
+    solid, c_s deep in the liquid -- which carry rounding noise amplified by
+    the regularised 1/|grad phi|^2 of the far tails; central differences of
+    such a loss do not converge as h -> 0, while the mixture c suppresses them
+    by p or 1 - p.)"""
+    from paper_2303_09671_amd.adjoint import FinalState, Workload
+    torch = torch_dev
+    if dim == 1:
+        runs = [dict(N=300, V=V, dt=I.run_dt(V), z0=80 * I.DX) for V in (0.1, 0.4)]
+        base = I.base_params(dim=1)
+        phi, cs, cl, offs = I.batch_fields(runs)
+        wl = Workload(params=base, fields0=(phi, cs, cl), nsteps=350, every=100, runs=runs, offsets=offs)
+        mask = torch.zeros(phi.size, dtype=torch.float64)
+        for r, o in zip(runs, offs):
+            mask[o:o + r["N"]] = 1.0
+    else:
+        p, _, pert = I.config_2d(nx=48, nz=40)
+        p = dict(p, V=0.5, z0=12 * I.DX)
+        f = tuple(a.ravel() for a in I.planar_front(2, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=3))
+        wl = Workload(params=p, fields0=f, nsteps=250, every=100)
+        mask = torch.ones(f[0].size, dtype=torch.float64)
+    mask = mask.cuda()
+    theta0 = np.array([1.2, 1.0, 1.0])
+    with torch.no_grad():
+        ref = FinalState.apply(torch.tensor([1.15, 1.05, 0.97], dtype=torch.float64), wl)
+
+    def mix(u):
+        ph = u[0]
+        p = ph ** 3 * (ph * (6.0 * ph - 15.0) + 10.0)  # quintic h (a_p = 0)
+        return p * u[1] + (1.0 - p) * u[2]
+
+    c_ref = mix(ref)
+
+    def loss(theta):
+        u = FinalState.apply(theta, wl)
+        return (mask * (u[0] - ref[0]) ** 2).sum() + (mask * (mix(u) - c_ref) ** 2).sum()
+
+    print(f"case: profile loss {dim}D", flush=True)
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    L = loss(th)
+    L.backward()
+    g = th.grad.numpy()
+    h = 1e-6
+    fd = np.zeros(3)
+    with torch.no_grad():
+        for i in range(3):
+            tp, tm = theta0.copy(), theta0.copy()
+            tp[i] += h
+            tm[i] -= h
+            fd[i] = (loss(torch.tensor(tp)).item() - loss(torch.tensor(tm)).item()) / (2 * h)
+    print(f"  grad {g} fd {fd}", flush=True)
+    for i in range(3):
+        assert abs(g[i] - fd[i]) <= 1e-5 * max(abs(fd[i]), 1e-3 * np.abs(fd).max()), (i, g, fd)
