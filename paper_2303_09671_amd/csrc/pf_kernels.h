@@ -44,9 +44,12 @@ __device__ __forceinline__ int map_axis(int g, int n, int periodic) {
 // (mostly L2 hits).  With a window shift the updated plane z is stored at z-1
 // and the fresh liquid layer at the top.
 // ---------------------------------------------------------------------------
+// 3D: one thread per tile column (TX * TY threads).  2D: one wave covers the
+// tile (TX = 62 columns) plus its two halo columns, so the cell stage of the
+// tile and halo and the TX + 1 x faces each take a single pass of the wave.
 template <int DIM, int TX, int TY>
 struct StreamGeom {
-  static constexpr int NT = TX * TY;
+  static constexpr int NT = (DIM == 2) ? TX + 2 : TX * TY;
   static constexpr int BX2 = TX + 4;
   static constexpr int BY2 = (DIM == 3) ? TY + 4 : 1;
   static constexpr int BX1 = TX + 2;
@@ -62,7 +65,7 @@ struct StreamGeom {
 };
 
 template <int DIM, int TX, int TY, bool APZ>
-__global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
+__global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
                                                     double* __restrict__ oph, double* __restrict__ ocs,
@@ -83,9 +86,11 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   const int ze = min(zb + zchunk, c.nz);
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long plane = (long long)nx * ny;
-  const int ox = tid % TX, oy = tid / TX;  // own column
+  // own column (2D: threads 1..TX; threads 0 and TX+1 take the halo columns)
+  const int ox = (DIM == 2) ? tid - 1 : tid % TX, oy = (DIM == 2) ? 0 : tid / TX;
+  const bool own = (DIM == 3) || (tid >= 1 && tid <= TX);
   const int gxo = x0 + ox, gyo = y0 + oy;
-  const bool own_valid = (gxo < nx) && (gyo < ny);
+  const bool own_valid = own && (gxo < nx) && (gyo < ny);
   auto slot3 = [](int gz) { return (gz + 9) % 3; };
 
   // Cell-stage positions of this thread on the tile plus in-plane halo 1:
@@ -96,12 +101,18 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
   constexpr int NCS = 2;
   constexpr int NHALO = G::P1 - G::NT;
-  static_assert(NHALO > 0 && NHALO <= G::NT, "tile shape: halo cells must fit one item per thread");
+  static_assert(DIM == 2 ? NHALO == 0 : (NHALO > 0 && NHALO <= G::NT),
+                "tile shape: halo cells must fit one item per thread");
   auto cs_pos = [&](int r, int& lx, int& ly) {
     if (r == 0) {
       lx = ox;
       ly = oy;
       return true;
+    }
+    if constexpr (DIM == 2) {
+      lx = ox;
+      ly = 0;
+      return false;
     }
     constexpr int NROW = (DIM == 3) ? 2 * G::BX1 : 0;
     const int h = min(tid, NHALO - 1);
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   // to wave 2 (x) and wave 3 (y), as the extra cells of the cell stage go to
   // waves 0 and 1, so the four waves carry equal work per plane.
   constexpr int NW = G::NT / 64;
-  constexpr int EX = G::NFX - G::NT, EY = G::NFY - G::NT;
+  constexpr int EX = (DIM == 2) ? 0 : G::NFX - G::NT, EY = G::NFY - G::NT;
   static_assert(EX >= 0 && EX <= 64 && (DIM == 2 || (EY >= 0 && EY <= 64)),
                 "tile shape: leftover faces must fit one wave");
   constexpr int WX = (2 < NW) ? 2 : NW - 1, WY = (3 < NW) ? 3 : NW - 1;
@@ -324,17 +335,21 @@ __global__ __launch_bounds__(TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c,
   cell_plane(zb - 1, true, true);
   cell_plane(zb, true, false);
   __syncthreads();
-  double FsD, FlD;  // flux through the face below the current plane
-  zface(zb - 1, FsD, FlD);
+  double FsD = 0.0, FlD = 0.0;  // flux through the face below the current plane
+  if (own) zface(zb - 1, FsD, FlD);
 
   int errbits = 0;
   for (int z = zb; z < ze; ++z) {
     cell_plane(z + 1, false, false);  // plane z+2 read from global memory
     __syncthreads();
-    face_item(std::integral_constant<int, 0>{}, z, ox, oy);
-    if constexpr (DIM == 3) face_item(std::integral_constant<int, 1>{}, z, ox, oy);
-    double FsU, FlU;
-    zface(z, FsU, FlU);
+    if constexpr (DIM == 3) {
+      face_item(std::integral_constant<int, 0>{}, z, ox, oy);
+      face_item(std::integral_constant<int, 1>{}, z, ox, oy);
+    } else if (tid <= TX) {
+      face_item(std::integral_constant<int, 0>{}, z, tid, 0);  // the TX + 1 x faces in one pass
+    }
+    double FsU = 0.0, FlU = 0.0;
+    if (own) zface(z, FsU, FlU);
     if (extra_x) face_item(std::integral_constant<int, 0>{}, z, TX, lex);
     if constexpr (DIM == 3)
       if (extra_y) face_item(std::integral_constant<int, 1>{}, z, ley, TY);

@@ -39,7 +39,7 @@ int fail(int code, const std::string& msg) {
 // grid column is cut into chunks so that the launch holds about `target`
 // workgroups (prologue cost: two extra planes of cell rates per chunk).
 constexpr int S3_TX = 32, S3_TY = 8;  // 3D: 256 threads (4 waves), 3 workgroups per CU
-constexpr int S2_TX = 64;             // 2D: 64 threads (1 wave)
+constexpr int S2_TX = 62;             // 2D: 62 columns + 2 halo columns = 64 threads (1 wave)
 
 int zchunk_for(int nz, long long tiles, long long target, int zmin) {
   long long split = std::max<long long>(1, (target + tiles - 1) / tiles);
@@ -251,8 +251,8 @@ int launch_stream(pf_handle* h, double* const src[3], double* const dst[3], long
     const int zc = h->zchunk;
     dim3 grid((c.nx + S2_TX - 1) / S2_TX, 1, (c.nz + zc - 1) / zc);
     auto k = apz ? pfk::k_stream<2, S2_TX, 1, true> : pfk::k_stream<2, S2_TX, 1, false>;
-    hipLaunchKernelGGL(k, grid, dim3(S2_TX), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1], dst[2], zc,
-                       tn, sn, sh, h->d_err);
+    hipLaunchKernelGGL(k, grid, dim3(S2_TX + 2), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1], dst[2],
+                       zc, tn, sn, sh, h->d_err);
   }
   PF_HIP(hipGetLastError());
   return PF_OK;
@@ -400,7 +400,7 @@ int pf_create(const pf_params* p, double* phi, double* cs, double* cl, void* str
       h->zchunk = zchunk_for(c.nz, tiles, 11LL * ncu, 16);  // ~3.7 rounds of 3 workgroups per CU
     } else {
       const long long tiles = (c.nx + S2_TX - 1) / S2_TX;
-      h->zchunk = zchunk_for(c.nz, tiles, 16LL * ncu, 8);  // 4 one-wave workgroups per SIMD
+      h->zchunk = zchunk_for(c.nz, tiles, 32LL * ncu, 4);  // chunks of 4 planes at 1024^2 (measured best)
     }
     if (const char* e = std::getenv("PF_ZCHUNK")) {  // tuning override
       const int v = std::atoi(e);
