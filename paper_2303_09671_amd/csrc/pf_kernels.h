@@ -316,6 +316,51 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     F0[f] = Fs;
     F1[f] = Fl;
   };
+  // 3D only: the face normal to in-plane axis K (runtime: 0 = x, 1 = y) on the
+  // low side of cell (fa, fb), with the gradient components ordered (normal,
+  // other in-plane, z) so that one code path serves both axes.
+  auto face_item_rt = [&](int K, int gz, int fa, int fb) {
+    const int RW = (K == 0) ? TX + 1 : TX;
+    const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
+    const int pt = (gz + 8) & 1;
+    const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
+    double* F0 = (K == 0) ? sfx[0] : sfy[0];
+    double* F1 = (K == 0) ? sfx[1] : sfy[1];
+    const int f = fb * RW + fa;
+    const int ax = (K == 0) ? fa - 1 : fa, ay = (K == 0) ? fb : fb - 1;
+    const int gface = (K == 0) ? x0 + fa : y0 + fb;
+    const int nk = (K == 0) ? nx : ny;
+    const int pk = (K == 0) ? c.px : c.py;
+    if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
+      F0[f] = 0.0;
+      F1[f] = 0.0;
+      return;
+    }
+    const int ia = G::i2(ax, ay), ib = G::i2(fa, fb);
+    const int ja = G::i1(ax, ay), jb = G::i1(fa, fb);
+    const int d2 = (K == 0) ? G::BX2 : 1, d1 = (K == 0) ? G::BX1 : 1;  // the other in-plane axis
+    double gph[3], gmu[3], gcs[3], gcl[3];
+    const double pa = su[s0][0][ia], pb = su[s0][0][ib];
+    const double ca = su[s0][1][ia], cb = su[s0][1][ib];
+    const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
+    gph[0] = pb - pa;
+    gmu[0] = smu[m0][jb] - smu[m0][ja];
+    gcs[0] = cb - ca;
+    gcl[0] = lb_ - la_;
+    gph[1] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
+    gmu[1] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
+    gcs[1] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
+    gcl[1] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
+    gph[2] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
+    gmu[2] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
+    gcs[2] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
+    gcl[2] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
+    const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
+    double Fs, Fl;
+    face_flux<3, 0, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+    F0[f] = Fs;
+    F1[f] = Fl;
+  };
   // Face items: every thread takes the x and y faces on the low side of its own
   // cell; the faces on the high side of the tile (TY of them in x, TX in y) go
   // to wave 2 (x) and wave 3 (y), as the extra cells of the cell stage go to
@@ -324,10 +369,11 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   constexpr int EX = (DIM == 2) ? 0 : G::NFX - G::NT, EY = G::NFY - G::NT;
   static_assert(EX >= 0 && EX <= 64 && (DIM == 2 || (EY >= 0 && EY <= 64)),
                 "tile shape: leftover faces must fit one wave");
-  constexpr int WX = (2 < NW) ? 2 : NW - 1, WY = (3 < NW) ? 3 : NW - 1;
-  const int lex = tid - 64 * WX, ley = tid - 64 * WY;
-  const bool extra_x = (EX > 0) && lex >= 0 && lex < EX;
-  const bool extra_y = (DIM == 3) && (EY > 0) && ley >= 0 && ley < EY;
+  // 3D: the TY + TX leftover faces go to one wave in a single pass (runtime axis).
+  static_assert(DIM == 2 || EX + EY <= 64, "tile shape: leftover faces must fit one wave");
+  constexpr int WE = NW - 1;
+  const int le = tid - 64 * WE;
+  const bool extra_f = (DIM == 3) && le >= 0 && le < EX + EY;
 
   // ---- prologue: ring = planes zb-1, zb, zb+1; rates of planes zb-1 and zb
   for (int g = zb - 1; g <= zb + 1; ++g) load_plane(g);
@@ -350,9 +396,12 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     }
     double FsU = 0.0, FlU = 0.0;
     if (own) zface(z, FsU, FlU);
-    if (extra_x) face_item(std::integral_constant<int, 0>{}, z, TX, lex);
-    if constexpr (DIM == 3)
-      if (extra_y) face_item(std::integral_constant<int, 1>{}, z, ley, TY);
+    if constexpr (DIM == 3) {
+      if (extra_f) {  // one call: lanes 0..EX-1 take x faces, the rest y faces
+        const int K = (le < EX) ? 0 : 1;
+        face_item_rt(K, z, (K == 0) ? TX : le - EX, (K == 0) ? le : TY);
+      }
+    }
     __syncthreads();
     if (own_valid) {
       const int s0 = slot3(z);
