@@ -3,8 +3,9 @@
 Sec. V.C tunes the source strength A, the shape parameter b and the interface
 width W so that the model's velocity-dependent partition coefficient follows a
 measured or simulated curve, and notes that several combinations give the same
-trapping.  Here the fit is driven by exact gradients of the simulated k(V)
-rather than by the asymptotic relation: each evaluation runs the checkpointed
+trapping.  The paper fits the asymptotic relation (Eq. partition1); here that
+relation only gives the starting point (asymptotic_start), and the fit itself
+is driven by exact gradients of the simulated k(V): each evaluation runs the checkpointed
 forward over the workload's runs (PartitionCoefficient), the adjoint backward
 gives dL/dtheta for L = sum_r (k_r - k*_r)^2, and a quasi-Newton step (BFGS
 with a backtracking line search) moves theta.  Every step of the forward and
@@ -22,7 +23,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import pf
+from . import asymptotics, pf
 from .adjoint import PartitionCoefficient, Workload
 
 THETA_LO = np.array([0.0, 0.25, 0.25])
@@ -54,6 +55,19 @@ def loss_and_grad(workload: Workload, k_target, theta):
     if not np.all(np.isfinite(g)):
         return np.inf, None, None
     return float(L.item()), g, k.detach().numpy()
+
+
+def asymptotic_start(workload: Workload, k_target, chi: float = 1.0):
+    """Starting theta for fit_theta from Eq. partition1 (asymptotics.start_theta):
+    the workload's current (A, M_phi, W) with A, or W where A has no effect on
+    the asymptotic curve, set to the value whose predicted k(V) best fits
+    k_target over the runs' velocities.  The result is clipped to the box."""
+    p = workload.params
+    Vs = [r["V"] for r in workload.runs]
+    theta, _ = asymptotics.start_theta(Vs, k_target, (p["A"], p["Mphi"], p["W"]), b=p["b"], Ds=p["Ds"],
+                                       ke=p["ke"], chi=chi, ap=p.get("ap", 0.0),
+                                       quintic=bool(p.get("quintic", 1)))
+    return np.clip(theta, THETA_LO, THETA_HI)
 
 
 def fit_theta(workload: Workload, k_target, theta0, iters: int = 20, max_step: float = 0.05,
