@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "liborc.so")
 
 #: Default nondimensional parameters (lengths in W0, time in W0^2/D_l, c in c_inf).
 DEFAULTS = dict(
-    dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0,
+    dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0, model=0,
     dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=1.2,
     b=1e-4, ap=0.0, inv_lT=1.0 / 444.0, V=0.1, z0=256 * 0.8, eps_grad=1e-20,
 )
@@ -38,7 +38,7 @@ DEFAULTS = dict(
 class _Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
-        ("quintic", C.c_int32), ("drag_variant", C.c_int32), ("pad_", C.c_int32),
+        ("quintic", C.c_int32), ("drag_variant", C.c_int32), ("model", C.c_int32),
         ("dx", C.c_double), ("dt", C.c_double), ("W", C.c_double), ("Mphi", C.c_double),
         ("lambda0", C.c_double), ("Ds", C.c_double), ("ke", C.c_double), ("A", C.c_double),
         ("b", C.c_double), ("ap", C.c_double), ("inv_lT", C.c_double), ("V", C.c_double),
@@ -99,6 +99,7 @@ def _cparams(p: dict) -> _Params:
         s.periodic[k] = int(per[k])
     s.quintic = int(p["quintic"])
     s.drag_variant = int(p["drag_variant"])
+    s.model = int(p.get("model", 0))
     for f in ("dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b", "ap", "inv_lT", "V", "z0",
               "eps_grad"):
         setattr(s, f, float(p[f]))

@@ -36,6 +36,16 @@
 //   * no-flux (mirror) boundaries on the growth axis, mirror or periodic on
 //     the transverse axes.
 //
+// model = 1 steps instead the variant with pointwise equal diffusion potentials,
+// mu_s = mu_l, which is the model of the paper's asymptotic analysis (Sec. II.C;
+// with A = 1 and b = k_e D_s/D_l it is the KKS model of Sec. IV, Eqs. KKS1,
+// KKS2).  The phase-field rate is Eq. phasefield_nonvar with mu_s = mu_l.  A
+// single conserved mixture c = p c_s + (1 - p) c_l follows the bracket of
+// Eq. solute_nonvar.  After each step the phase concentrations are recovered from
+// c and the new phi by the equal-potential condition of the dilute ideal alloy
+// (Eq. dil1: ln(c_s/k_e) = ln c_l), i.e. c_s = k_e c_l and
+// c_l = c / (k_e p + 1 - p).
+//
 // The step is templated on the scalar type so that the same code also runs on
 // dual numbers, which gives exact forward-mode directional derivatives (JVPs)
 // used to check the hand-written adjoint of the GPU library.
@@ -82,7 +92,7 @@ struct OrcParams {
   int32_t periodic[3];  // transverse axes: 1 periodic, 0 mirror; growth axis ignored (mirror)
   int32_t quintic;      // 1: h = phi^3(6phi^2-15phi+10); 0: h = phi^2(3-2phi)
   int32_t drag_variant; // 0: drive from Eq. model18 (used); 1: printed reduced form (mutation tests only)
-  int32_t pad_;
+  int32_t model;        // 0: separate kinetics of c_s and c_l; 1: mu_s = mu_l imposed pointwise
   double dx, dt;
   double W;        // interface width / W0
   double Mphi;     // phi mobility in units of 1/alpha at W = W0; alpha = W / Mphi
@@ -195,6 +205,10 @@ Pointwise<T> pointwise(const OrcParams& P, const WP<T>& w, T phi, T cs, T cl, do
   T ls = dlog(cs), ll = dlog(cl);
   r.dmu = ls - ll - std::log(P.ke);
   r.mubar = r.p * (ls - std::log(P.ke)) + r.q * ll;
+  if (P.model == 1) {  // mu_s = mu_l = mu = ln c_l imposed
+    r.dmu = 0.0;
+    r.mubar = ll;
+  }
   r.dc = cs - cl;
   // Local mobilities M_i = D_i c_i / Omega in units of c_inf D_l / Omega.
   r.Ms = P.Ds * cs;
@@ -321,6 +335,57 @@ bool face_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, 
   return true;
 }
 
+// Solute flux of the equal-potential model (the bracket of Eq. solute_nonvar
+// with mu_s = mu_l = mu) through the face between cell c and c + e_k, with the
+// local mobilities (M_s grad mu = D_s grad c_s, M_l grad mu = grad c_l):
+//   J_k = q_n (n n^T grad mu)_k + p D_s ((1 - n n^T) grad c_s)_k + (1 - p) ((1 - n n^T) grad c_l)_k
+//       + (1 - A)(c_s - c_l) a(phi) phi_t (grad phi)_k / |grad phi|^2,
+// a(phi) = (M_s - b M_l) p (1 - p) / Mbar (Eq. shape_function), face means and
+// face gradients as in face_flux.  Returns false for a boundary face.
+template <class T>
+bool mixture_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, const T* cs, const T* cl,
+                  const StepWork<T>& S, const int c[3], int k, T& J) {
+  const double dx = P.dx;
+  bool periodic_axis = g.per[k] && k != g.dim - 1;
+  if (!periodic_axis && c[k] == g.n[k] - 1) {
+    J = 0.0;
+    return false;
+  }
+  long a = g.lin(c);
+  long bidx = g.at(c, k, +1);
+  int cb[3] = {c[0], c[1], c[2]};
+  cb[k] = g.map(c[k] + 1, k);
+  T phif = 0.5 * (phi[a] + phi[bidx]);
+  T csf = 0.5 * (cs[a] + cs[bidx]);
+  T clf = 0.5 * (cl[a] + cl[bidx]);
+  T phitf = 0.5 * (S.phit[a] + S.phit[bidx]);
+  T pf = p_of(phif, P.quintic, P.ap);
+  T qf = p_of(1.0 - phif, P.quintic, P.ap);
+  const T* fld[4] = {phi, S.mubar.data(), cs, cl};
+  T grad[4][3];
+  for (int f = 0; f < 4; ++f)
+    for (int j = 0; j < P.dim; ++j)
+      grad[f][j] = (j == k) ? (fld[f][bidx] - fld[f][a]) / dx
+                            : 0.5 * (cdiff(g, fld[f], c, j, dx) + cdiff(g, fld[f], cb, j, dx));
+  T G = 0.0, dmu = 0.0, dcs = 0.0, dcl = 0.0;
+  for (int j = 0; j < P.dim; ++j) {
+    G = G + grad[0][j] * grad[0][j];
+    dmu = dmu + grad[0][j] * grad[1][j];
+    dcs = dcs + grad[0][j] * grad[2][j];
+    dcl = dcl + grad[0][j] * grad[3][j];
+  }
+  T gam = G / (G * G + P.eps_grad * P.eps_grad);
+  T Ms = P.Ds * csf, Ml = clf;
+  T Mbar = Ms * qf + P.b * Ml * pf;
+  T qn = Ms * Ml * (P.b * pf + qf) / Mbar;       // Eq. normal2 with h_n of Eq. interpolation1
+  T a_shape = (Ms - P.b * Ml) * pf * qf / Mbar;  // Eq. shape_function
+  T normal = qn * gam * dmu * grad[0][k];
+  T tang = pf * P.Ds * (grad[2][k] - gam * dcs * grad[0][k]) + qf * (grad[3][k] - gam * dcl * grad[0][k]);
+  T anti = (1.0 - w.A) * (csf - clf) * a_shape * phitf * grad[0][k] * gam;
+  J = normal + tang + anti;
+  return true;
+}
+
 // One forward-Euler step n -> n+1 in place.  s_shift is the number of window
 // shifts done so far (lab height of cell iz is (iz + s + 1/2) dx).
 template <class T>
@@ -354,7 +419,7 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
       for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
         long i = g.lin(c);
         T divs = 0.0, divl = 0.0;
-        for (int k = 0; k < P.dim; ++k) {
+        for (int k = 0; k < P.dim && P.model == 0; ++k) {
           T jsp, jlp, jsm, jlm;
           face_flux(P, w, g, phi, cs, cl, S, c, k, jsp, jlp);
           bool periodic_axis = g.per[k] && k != g.dim - 1;
@@ -370,10 +435,32 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
           divl = divl + (jlp - jlm) / P.dx;
         }
         const Pointwise<T>& q = S.pw[i];
+        nphi[i] = phi[i] + P.dt * S.phit[i];
+        if (P.model == 1) {
+          // conserved mixture c, then the equal-potential split at the new phi
+          T divc = 0.0;
+          for (int k = 0; k < P.dim; ++k) {
+            T jp, jm;
+            mixture_flux(P, w, g, phi, cs, cl, S, c, k, jp);
+            bool periodic_axis = g.per[k] && k != g.dim - 1;
+            if (!periodic_axis && c[k] == 0) {
+              jm = 0.0;
+            } else {
+              int cm[3] = {c[0], c[1], c[2]};
+              cm[k] = g.map(c[k] - 1, k);
+              mixture_flux(P, w, g, phi, cs, cl, S, cm, k, jm);
+            }
+            divc = divc + (jp - jm) / P.dx;
+          }
+          T cmix = q.p * cs[i] + q.q * cl[i] + P.dt * divc;
+          T pn = p_of(nphi[i], P.quintic, P.ap), qn = p_of(1.0 - nphi[i], P.quintic, P.ap);
+          ncl[i] = cmix / (P.ke * pn + qn);
+          ncs[i] = P.ke * ncl[i];
+          continue;
+        }
         T src = -w.A * q.dc * q.dp * S.phit[i];  // S g'(phi) phi_t with S = -A(c_s - c_l)
         ncs[i] = cs[i] + P.dt * (divs + src);
         ncl[i] = cl[i] + P.dt * (divl + src);
-        nphi[i] = phi[i] + P.dt * S.phit[i];
       }
   // Moving window.
   const double tn1 = (double)(n + 1) * P.dt;
