@@ -267,6 +267,23 @@ def main():
         extra["batch_256_runs"] = bench_batch(torch, pf, 2000)
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
+        # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
+        pe = dict(p3, model=1, eps_grad=1e-4)
+        te, ke_, ce, _, _ = time_domain(torch, pf, pe, pert3, 500, 10)
+        ae = BYTES_PER_CELL * ce / (ke_ / 500) / 1e9
+        extra["equal_potential_3d_256"] = dict(kernel="k_stream<3,32,8,APZ,EQ=1>", kernel_avg_us=ke_ / 500 * 1e6,
+                                               cell_updates_per_s=ce * 500 / te, achieved_GBs=ae,
+                                               frac=ae / HBM_PEAK_GBS)
+        t1e = [dev(torch, a) for a in f1]
+        h1e = pf.pf_create(dict(p1, model=1, eps_grad=1e-4), *t1e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pf.pf_step(h1e, steps1)
+        torch.cuda.synchronize()
+        d1e = time.perf_counter() - t0
+        _, cme, _ = pf.pf_solute(h1e)
+        extra["equal_potential_1d_1024_20000_steps"] = dict(seconds=d1e, cell_updates_per_s=1024 * steps1 / d1e,
+                                                            k=float(1.0 / cme[0]))
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -73,7 +73,16 @@ typedef struct pf_params {
   double eps_grad;      /* eps of 1/|grad phi|^2 ~ G / (G^2 + eps^2), G = |grad phi|^2 */
   /* batched 1D runs: nbatch > 0 and dim == 1.  Host arrays, copied by pf_create. */
   int32_t nbatch;
-  int32_t pad_;
+  int32_t model;        /* 0: set-2 equations, separate kinetics of c_s and c_l (above);
+                         * 1: equal diffusion potentials imposed pointwise, mu_s = mu_l
+                         *    (the model of the asymptotic analysis, Sec. II.C; with A = 1
+                         *    and b = k_e D_s/D_l the KKS model, Sec. IV, Eqs. KKS1, KKS2):
+                         *    phi_t from Eq. phasefield_nonvar with mu_s = mu_l, the mixture
+                         *    c = p c_s + (1-p) c_l conserved with the flux of Eq.
+                         *    solute_nonvar, and after every step c_l = c / (k_e p + 1 - p),
+                         *    c_s = k_e c_l (Eq. dil1).  The fields keep the (phi, c_s, c_l)
+                         *    layout; the first step takes c from the fields as given.  The
+                         *    adjoint entry points return PF_EINVAL for model 1.           */
   const int32_t* run_n;    /* cells of run r (3 <= run_n[r] <= 8192)               */
   const int64_t* run_off;  /* first cell of run r in the field arrays              */
   const double* run_V;     /* pulling speed of run r                               */
@@ -137,7 +146,7 @@ int pf_front(pf_handle* h, double* z_mean, double* z_min, double* z_max, double*
  * function): PF_OK, PF_ENONFINITE or PF_ENEGCONC.  Synchronous; clears it. */
 int pf_check(pf_handle* h);
 
-/* Adjoint of one step (transpose of the Jacobian of step n -> n + 1):
+/* Adjoint of one step (transpose of the Jacobian of step n -> n + 1) of model 0:
  *   lam_n = (d u^{n+1} / d u^n)^T lam_np1,
  *   dtheta += (d u^{n+1} / d theta)^T lam_np1,  theta = (A, M_phi, W),
  * with alpha = W / M_phi and lambda = lambda0 W (gamma, Omega, D and the grid

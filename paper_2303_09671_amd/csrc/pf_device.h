@@ -2,6 +2,7 @@
 //
 // The per-cell and per-face formulas of the staggered scheme for the set-2
 // equations of motion (Sec. II: Eqs. cs_nonvar, cl_nonvar, phasefield_nonvar,
+// and, for the variant with mu_s = mu_l imposed, Eq. solute_nonvar,
 // drive of Eq. model18 reduced to dG_c - D (c_s - c_l)(mu_s - mu_l); Sec. III:
 // dilute ideal alloy, Eqs. dil5.2, ds3; Sec. V.A: central gradients at cells,
 // compact normal differences at faces, face-mean mobilities and anti-trapping).
@@ -174,21 +175,22 @@ __device__ __forceinline__ double cell_rate(const Const& c, double cleq, double 
   return num * frcp(den);
 }
 
-template <bool APZ>
+// EQ: the equal-potential model (mu_s = mu_l = ln c_l imposed): dmu = 0.
+template <bool APZ, bool EQ = false>
 __device__ __forceinline__ void cell_core(const Const& c, double cleq, double phi, double cs, double cl, double G,
                                           double dot, double Wlap, double eps2x, double onemAx, double& phit,
                                           double& mubar) {
   double p, q, dp;
   interp<APZ>(c, phi, p, q, dp);
   const double ll = flog(cl);
-  const double dmu = flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
+  const double dmu = EQ ? 0.0 : flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
   mubar = ll + p * dmu;
   phit = cell_rate(c, cleq, phi, cs, cl, dmu, p, q, dp, G, dot, Wlap, eps2x, onemAx);
 }
 
 // g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
 // compact Laplacian of phi.
-template <int DIM, bool APZ = false>
+template <int DIM, bool APZ = false, bool EQ = false>
 __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
                                            const double* gph, const double* gcs, const double* gcl,
                                            double lap, double& phit, double& mubar) {
@@ -198,12 +200,12 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
     G += gph[k] * gph[k];
     dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
   }
-  cell_core<APZ>(c, cleq, phi, cs, cl, G, dot, c.W2 * lap, c.eps2, c.onemA, phit, mubar);
+  cell_core<APZ, EQ>(c, cleq, phi, cs, cl, G, dot, c.W2 * lap, c.eps2, c.onemA, phit, mubar);
 }
 
 // The same from plain differences: d*[k] = u_{+k} - u_{-k} and lsum the sum over
 // axes of u_{+k} - 2 u + u_{-k} (k = 1 / (4 dx^2)).
-template <int DIM, bool APZ = false>
+template <int DIM, bool APZ = false, bool EQ = false>
 __device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, double phi, double cs, double cl,
                                                const double* dph, const double* dcs, const double* dcl,
                                                double lsum, double& phit, double& mubar) {
@@ -213,7 +215,7 @@ __device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, doub
     G += dph[k] * dph[k];
     dot += (c.Ds * dcs[k] - c.b * dcl[k]) * dph[k];
   }
-  cell_core<APZ>(c, cleq, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
+  cell_core<APZ, EQ>(c, cleq, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)
@@ -228,7 +230,11 @@ __device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, doub
 // Returned: dx times the fluxes (divergence = sum of differences / dx^2).  In
 // scaled units G' = dx^2 G, eps'^2 = dx^4 eps^2 and R' = R / dx, which leaves
 // every term but the anti-trapping one (factor dx^2) unchanged in form.
-template <int DIM, int K, bool APZ = false>
+// EQ (equal-potential model): Fs returns the mixture flux p F_s + (1-p) F_l,
+// the bracket of Eq. solute_nonvar (its anti-trapping part is
+// (1-A)(c_s - c_l) a(phi) phi_t n / |grad phi| with a of Eq. shape_function);
+// Fl is zero.
+template <int DIM, int K, bool APZ = false, bool EQ = false>
 __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf, double clf, double ptf,
                                           const double* gph, const double* gmu, const double* gcs,
                                           const double* gcl, double& Fs, double& Fl) {
@@ -254,6 +260,20 @@ __device__ __forceinline__ void face_flux(const Const& c, double phf, double csf
   const double MbR = Mb * R;
   Fs = nrm + c.Ds * (gcs[K] - dcs * MbR) + at * ms;
   Fl = nrm + (gcl[K] - dcl * MbR) - at * ml;
+  if constexpr (EQ) {
+    Fs = p * Fs + q * Fl;
+    Fl = 0.0;
+  }
+}
+
+// Equal-potential split of the mixture concentration at phase field phi
+// (dilute ideal alloy, mu_s = mu_l): c_l = c / (k_e p + 1 - p), c_s = k_e c_l.
+template <bool APZ>
+__device__ __forceinline__ void eq_split(const Const& c, double phi, double cmix, double& cs, double& cl) {
+  double p, q;
+  interp_pq<APZ>(c, phi, p, q);
+  cl = cmix * frcp(__builtin_fma(c.ke, p, q));
+  cs = c.ke * cl;
 }
 
 // Error word bits.

@@ -64,7 +64,7 @@ struct StreamGeom {
   __device__ static __forceinline__ int i1(int lx, int ly) { return (lx + 1) + BX1 * (ly + OY1); }
 };
 
-template <int DIM, int TX, int TY, bool APZ>
+template <int DIM, int TX, int TY, bool APZ, bool EQ>
 __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
@@ -220,7 +220,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       gcl[DIM - 1] = upL - dnL;
       lap += (upP - 2.0 * ph + dnP);
       double phit, mubar;
-      cell_stage_raw<DIM, APZ>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
+      cell_stage_raw<DIM, APZ, EQ>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
       spt[pt][i] = phit;
       smu[mu][i] = mubar;
     }
@@ -260,8 +260,8 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       gcl[1] = (su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2]);
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
-    face_flux<DIM, DIM - 1, APZ>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs, gcl, Fs,
-                            Fl);
+    face_flux<DIM, DIM - 1, APZ, EQ>(c, 0.5 * (pa_ + pb_), 0.5 * (ca + cb), 0.5 * (la + lb), ptf, gph, gmu, gcs,
+                                     gcl, Fs, Fl);
   };
 
   // The face normal to in-plane axis K (0 = x, 1 = y) of plane gz on the low
@@ -283,7 +283,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int pk = (K == 0) ? c.px : c.py;
     if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
       F0[f] = 0.0;
-      F1[f] = 0.0;
+      if constexpr (!EQ) F1[f] = 0.0;
       return;
     }
     const int ia = G::i2(ax, ay), ib = G::i2(bx, by);
@@ -312,9 +312,10 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
     const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
     double Fs, Fl;
-    face_flux<DIM, K, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+    face_flux<DIM, K, APZ, EQ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs,
+                               Fl);
     F0[f] = Fs;
-    F1[f] = Fl;
+    if constexpr (!EQ) F1[f] = Fl;
   };
   // 3D only: the face normal to in-plane axis K (runtime: 0 = x, 1 = y) on the
   // low side of cell (fa, fb), with the gradient components ordered (normal,
@@ -333,7 +334,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int pk = (K == 0) ? c.px : c.py;
     if ((!pk && (gface == 0 || gface >= nk)) || gface > nk) {
       F0[f] = 0.0;
-      F1[f] = 0.0;
+      if constexpr (!EQ) F1[f] = 0.0;
       return;
     }
     const int ia = G::i2(ax, ay), ib = G::i2(fa, fb);
@@ -357,9 +358,9 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     gcl[2] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
     const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
     double Fs, Fl;
-    face_flux<3, 0, APZ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
+    face_flux<3, 0, APZ, EQ>(c, 0.5 * (pa + pb), 0.5 * (ca + cb), 0.5 * (la_ + lb_), ptf, gph, gmu, gcs, gcl, Fs, Fl);
     F0[f] = Fs;
-    F1[f] = Fl;
+    if constexpr (!EQ) F1[f] = Fl;
   };
   // Face items: every thread takes the x and y faces on the low side of its own
   // cell; the faces on the high side of the tile (TY of them in x, TX in y) go
@@ -409,19 +410,24 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       const double ph = su[s0][0][ic], cs = su[s0][1][ic], cl = su[s0][2][ic];
       const double pt = spt[(z + 8) & 1][i1];
       double divs = sfx[0][oy * (TX + 1) + ox + 1] - sfx[0][oy * (TX + 1) + ox];
-      double divl = sfx[1][oy * (TX + 1) + ox + 1] - sfx[1][oy * (TX + 1) + ox];
-      if (DIM == 3) {
-        divs += sfy[0][(oy + 1) * TX + ox] - sfy[0][oy * TX + ox];
-        divl += sfy[1][(oy + 1) * TX + ox] - sfy[1][oy * TX + ox];
-      }
+      if (DIM == 3) divs += sfy[0][(oy + 1) * TX + ox] - sfy[0][oy * TX + ox];
       divs += FsU - FsD;
-      divl += FlU - FlD;
-      double p, q, dp;
-      interp<APZ>(c, ph, p, q, dp);
-      const double src = -c.A * (cs - cl) * dp * pt;
-      const double ncs = cs + c.dt * (divs * c.inv_dx2 + src);
-      const double ncl = cl + c.dt * (divl * c.inv_dx2 + src);
       const double nph = ph + c.dt * pt;
+      double ncs, ncl;
+      if constexpr (EQ) {  // conserved mixture, then the equal-potential split at the new phi
+        double p, q;
+        interp_pq<APZ>(c, ph, p, q);
+        eq_split<APZ>(c, nph, p * cs + q * cl + c.dt * divs * c.inv_dx2, ncs, ncl);
+      } else {
+        double divl = sfx[1][oy * (TX + 1) + ox + 1] - sfx[1][oy * (TX + 1) + ox];
+        if (DIM == 3) divl += sfy[1][(oy + 1) * TX + ox] - sfy[1][oy * TX + ox];
+        divl += FlU - FlD;
+        double p, q, dp;
+        interp<APZ>(c, ph, p, q, dp);
+        const double src = -c.A * (cs - cl) * dp * pt;
+        ncs = cs + c.dt * (divs * c.inv_dx2 + src);
+        ncl = cl + c.dt * (divl * c.inv_dx2 + src);
+      }
       errbits |= check_bits(nph, ncs, ncl);
       const long long col = (long long)gxo + (long long)nx * gyo;
       if (!do_shift) {
@@ -474,7 +480,7 @@ struct RunTab {
 
 // One run (the block's) for nsteps steps; CM >= ceil(N / R1_THREADS) cells per
 // thread are held in registers.  xe/xd are the block's exchange buffers.
-template <int CM, bool APZ>
+template <int CM, bool APZ, bool EQ>
 __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int r, double* __restrict__ gph,
                                            double* __restrict__ gcs, double* __restrict__ gcl, long long n0,
                                            long long nsteps, int do_shift, int* __restrict__ err,
@@ -574,7 +580,7 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
         const double lap = pp - 2.0 * P[k] + pm;
         const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
         const double cleq = cleq_at(c, zlab, tn, V, z0);
-        cell_stage_raw<1, APZ>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
+        cell_stage_raw<1, APZ, EQ>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
       }
     }
     // exchange 2: phi_t and mu_bar of the chunk edges
@@ -619,8 +625,8 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
       double g1[1] = {mb - ma};
       double g2[1] = {sb - sa};
       double g3[1] = {lb - la};
-      face_flux<1, 0, APZ>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3, Fs,
-                           Fl);
+      face_flux<1, 0, APZ, EQ>(c, 0.5 * (pa + pb), 0.5 * (sa + sb), 0.5 * (la + lb), 0.5 * (ta + tb), g0, g1, g2, g3,
+                               Fs, Fl);
     };
     double FsL, FlL;
     face(0, FsL, FlL);
@@ -629,12 +635,20 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
       if (k < cnt) {
         double FsR, FlR;
         face(k + 1, FsR, FlR);
-        double p, q, dp;
-        interp<APZ>(c, P[k], p, q, dp);
-        const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
-        const double ns = S[k] + dt * ((FsR - FsL) * c.inv_dx2 + src);
-        const double nl = L[k] + dt * ((FlR - FlL) * c.inv_dx2 + src);
-        P[k] = P[k] + dt * PT[k];
+        double ns, nl;
+        const double np_ = P[k] + dt * PT[k];
+        if constexpr (EQ) {  // conserved mixture, then the equal-potential split at the new phi
+          double p, q;
+          interp_pq<APZ>(c, P[k], p, q);
+          eq_split<APZ>(c, np_, p * S[k] + q * L[k] + dt * (FsR - FsL) * c.inv_dx2, ns, nl);
+        } else {
+          double p, q, dp;
+          interp<APZ>(c, P[k], p, q, dp);
+          const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
+          ns = S[k] + dt * ((FsR - FsL) * c.inv_dx2 + src);
+          nl = L[k] + dt * ((FlR - FlL) * c.inv_dx2 + src);
+        }
+        P[k] = np_;
         S[k] = ns;
         L[k] = nl;
         errbits |= check_bits(P[k], S[k], L[k]);
@@ -683,7 +697,7 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
   if (errbits) atomicOr(err, errbits);
 }
 
-template <bool APZ>
+template <bool APZ, bool EQ>
 __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double* __restrict__ gph,
                                                       double* __restrict__ gcs, double* __restrict__ gcl,
                                                       long long n0, long long nsteps, int do_shift,
@@ -696,13 +710,13 @@ __global__ __launch_bounds__(R1_THREADS) void k_run1d(Const c, RunTab rt, double
   const int C = (rt.n[r] + R1_THREADS - 1) / R1_THREADS;
   // register arrays sized to the run: short runs get short unrolled loops
   if (C <= 1)
-    run1d_body<1, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+    run1d_body<1, APZ, EQ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
   else if (C <= 2)
-    run1d_body<2, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+    run1d_body<2, APZ, EQ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
   else if (C <= 4)
-    run1d_body<4, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+    run1d_body<4, APZ, EQ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
   else
-    run1d_body<R1_CMAX, APZ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
+    run1d_body<R1_CMAX, APZ, EQ>(c, rt, r, gph, gcs, gcl, n0, nsteps, do_shift, err, tph, tcs, tcl, tstride, xe, xd);
 }
 
 // ---------------------------------------------------------------------------

@@ -168,6 +168,7 @@ int validate(const pf_params& p) {
       !std::isfinite(p.A) || !std::isfinite(p.ap))
     return fail(PF_EINVAL, "non-finite parameter");
   if (!interp_admissible(p)) return fail(PF_EINVAL, "b and a_p give q_n < 0 or p outside [0, 1]");
+  if (p.model != 0 && p.model != 1) return fail(PF_EINVAL, "model must be 0 or 1");
   if (p.nbatch < 0) return fail(PF_EINVAL, "nbatch < 0");
   if (p.nbatch > 0) {
     if (p.dim != 1) return fail(PF_EINVAL, "batched mode needs dim == 1");
@@ -240,17 +241,19 @@ int launch_stream(pf_handle* h, double* const src[3], double* const dst[3], long
   const double tn = (double)n * c.dt;
   const double sn = std::floor(c.V * tn / c.dx);
   const int sh = (h->p.shift && std::floor(c.V * ((double)(n + 1) * c.dt) / c.dx) > sn) ? 1 : 0;
-  const bool apz = (c.ap == 0.0);
+  const bool apz = (c.ap == 0.0), eq = (h->p.model == 1);
   if (c.dim == 3) {
     const int zc = h->zchunk;
     dim3 grid((c.nx + S3_TX - 1) / S3_TX, (c.ny + S3_TY - 1) / S3_TY, (c.nz + zc - 1) / zc);
-    auto k = apz ? pfk::k_stream<3, S3_TX, S3_TY, true> : pfk::k_stream<3, S3_TX, S3_TY, false>;
+    auto k = eq ? (apz ? pfk::k_stream<3, S3_TX, S3_TY, true, true> : pfk::k_stream<3, S3_TX, S3_TY, false, true>)
+                : (apz ? pfk::k_stream<3, S3_TX, S3_TY, true, false> : pfk::k_stream<3, S3_TX, S3_TY, false, false>);
     hipLaunchKernelGGL(k, grid, dim3(S3_TX * S3_TY), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1],
                        dst[2], zc, tn, sn, sh, h->d_err);
   } else {
     const int zc = h->zchunk;
     dim3 grid((c.nx + S2_TX - 1) / S2_TX, 1, (c.nz + zc - 1) / zc);
-    auto k = apz ? pfk::k_stream<2, S2_TX, 1, true> : pfk::k_stream<2, S2_TX, 1, false>;
+    auto k = eq ? (apz ? pfk::k_stream<2, S2_TX, 1, true, true> : pfk::k_stream<2, S2_TX, 1, false, true>)
+                : (apz ? pfk::k_stream<2, S2_TX, 1, true, false> : pfk::k_stream<2, S2_TX, 1, false, false>);
     hipLaunchKernelGGL(k, grid, dim3(S2_TX + 2), 0, h->stream, c, src[0], src[1], src[2], dst[0], dst[1], dst[2],
                        zc, tn, sn, sh, h->d_err);
   }
@@ -425,7 +428,9 @@ static int step_impl(pf_handle* h, int64_t nsteps, double* const traj[3], int64_
       double* t0 = traj[0] ? traj[0] + done * stride : nullptr;
       double* t1 = traj[1] ? traj[1] + done * stride : nullptr;
       double* t2 = traj[2] ? traj[2] + done * stride : nullptr;
-      auto k = (h->c.ap == 0.0) ? pfk::k_run1d<true> : pfk::k_run1d<false>;
+      const bool apz = (h->c.ap == 0.0), eq = (h->p.model == 1);
+      auto k = eq ? (apz ? pfk::k_run1d<true, true> : pfk::k_run1d<false, true>)
+                  : (apz ? pfk::k_run1d<true, false> : pfk::k_run1d<false, false>);
       hipLaunchKernelGGL(k, dim3(h->nrun), dim3(pfk::R1_THREADS), 0, h->stream, h->c, h->runtab(),
                          h->f[0], h->f[1], h->f[2], (long long)(h->n + done), chunk, h->p.shift, h->d_err, t0, t1,
                          t2, (long long)stride);
@@ -603,6 +608,7 @@ int pf_kv_seed(pf_handle* h, const double* dL_dk, double* const lam[3]) {
 static int adj_prepare(pf_handle* h, int* nblk_out) {
   const pfk::Const& c = h->c;
   int nblk = 0;
+  if (h->p.model != 0) return fail(PF_EINVAL, "the adjoint step is built for model 0");
   if (h->batched) {
     if (!h->d_tiles) {
       std::vector<pfadj::Tile1> tiles;

@@ -38,7 +38,7 @@ class pf_params(C.Structure):
         ("lambda0", C.c_double), ("Ds", C.c_double), ("ke", C.c_double), ("A", C.c_double),
         ("b", C.c_double), ("ap", C.c_double), ("inv_lT", C.c_double), ("V", C.c_double),
         ("z0", C.c_double), ("eps_grad", C.c_double),
-        ("nbatch", C.c_int32), ("pad_", C.c_int32),
+        ("nbatch", C.c_int32), ("model", C.c_int32),
         ("run_n", C.POINTER(C.c_int32)), ("run_off", C.POINTER(C.c_int64)), ("run_V", C.POINTER(C.c_double)),
         ("run_dt", C.POINTER(C.c_double)), ("run_z0", C.POINTER(C.c_double)),
     ]
@@ -121,6 +121,7 @@ def _make_params(p: dict, runs=None, offsets=None):
     s.quintic = int(p.get("quintic", 1))
     s.shift = int(p.get("shift", 1))
     s.check_every = int(p.get("check_every", 0))
+    s.model = int(p.get("model", 0))
     for f in ("dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b", "ap", "inv_lT", "V", "z0", "eps_grad"):
         setattr(s, f, float(p[f]))
     keep = []

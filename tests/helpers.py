@@ -5,7 +5,7 @@ import numpy as np
 from paper_2303_09671_amd import inputs as I
 
 ORACLE_KEYS = ("dim", "n", "periodic", "quintic", "dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b",
-               "ap", "inv_lT", "V", "z0", "eps_grad")
+               "ap", "inv_lT", "V", "z0", "eps_grad", "model")
 
 TOL = 1e-10  # max relative field error: max|x - ref| / max|ref| per field
 

@@ -1,0 +1,150 @@
+"""GPU parity of the equal-potential model (model = 1: mu_s = mu_l imposed;
+KKS for A = 1 and b = k_e D_s/D_l) against the CPU oracle, through the C ABI.
+
+Same bar as the separate-kinetics step: max relative field error <= 1e-10
+per field after the whole run.  Cases: the KKS special case and A = 1.2 in 1D,
+uneven batched runs (1..8 cells per thread), 2D and 3D grids with ragged tiles,
+mirror and periodic transverse axes and window shifts, and a nonzero a_p.  Also:
+the split c_s = k_e c_l holds on the GPU output, closed runs conserve the
+mixture, and the adjoint entry points refuse model 1.
+"""
+import numpy as np
+import pytest
+
+from paper_2303_09671_amd import inputs as I
+from tests.helpers import TOL, assert_parity, oracle_batch, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def _run_gpu(torch, p, fields, nsteps, runs=None, offsets=None):
+    from paper_2303_09671_amd import pf
+    t = [_dev(torch, a) for a in fields]
+    h = pf.pf_create(p, *t, runs=runs, offsets=offsets)
+    pf.pf_step(h, nsteps)
+    torch.cuda.synchronize()
+    assert pf.pf_check(h) == pf.PF_OK
+    return h, t, [x.cpu().numpy() for x in t]
+
+
+def _split_ok(ke, cs, cl):
+    assert np.max(np.abs(cs - ke * cl) / cl) < 1e-15
+
+
+KKS = dict(model=1, A=1.0, b=I.ALLOY["ke"] * I.ALLOY["Ds"])
+EQ12 = dict(model=1, A=1.2, eps_grad=1e-4)
+
+
+@pytest.mark.parametrize("variant", ["kks", "A1.2"])
+def test_1d(torch_dev, oracle, variant):
+    p, _ = I.config_1d()
+    p = dict(p, **(KKS if variant == "kks" else EQ12))
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    steps = 4000
+    print(f"case: equal-potential 1D N=1024 {variant} steps={steps}", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert ref[3] > 0
+    assert_parity(g, ref[:3], what=f"equal 1D {variant}")
+    _split_ok(p["ke"], g[1], g[2])
+    from paper_2303_09671_amd import pf
+    tot, cm, _ = pf.pf_solute(h)
+    rt, rcm, _ = oracle.solute(oracle_params(oracle, p), *ref[:3])
+    assert abs(cm[0] - rcm) <= TOL * rcm and abs(tot[0] - rt) <= 1e-12 * abs(rt)
+
+
+def test_1d_batch(torch_dev, oracle):
+    Ns = (600, 1025, 3001, 8192, 77)
+    runs = []
+    for i, N in enumerate(Ns):
+        V = [0.05, 0.1, 0.3, 0.2, 0.02][i]
+        runs.append(dict(N=N, V=V, dt=I.run_dt(V), z0=(N // 4) * I.DX))
+    base = dict(I.base_params(dim=1), **EQ12)
+    phi, cs, cl, offs = I.batch_fields(runs)
+    steps = 1500
+    print(f"case: equal-potential batch {Ns} steps={steps}", flush=True)
+    refs = oracle_batch(oracle, base, runs, steps)
+    h, t, g = _run_gpu(torch_dev, base, (phi, cs, cl), steps, runs=runs, offsets=offs)
+    for r, o, ref in zip(runs, offs, refs):
+        gr = [a[o:o + r["N"]] for a in g]
+        assert_parity(gr, ref, what=f"equal run N={r['N']}")
+        _split_ok(base["ke"], gr[1], gr[2])
+
+
+@pytest.mark.parametrize("dim,periodic,extra", [(2, 1, {}), (2, 0, dict(ap=-1.5)), (3, (1, 1), {}),
+                                                (3, (0, 1), dict(ap=-2.0))])
+def test_2d_3d_ragged_with_shift(torch_dev, oracle, dim, periodic, extra):
+    if dim == 2:
+        p, _, pert = I.config_2d(nx=150, nz=75)
+        p = dict(p, periodic=(periodic, 0, 0), V=0.5)
+        steps, nshift = 260, 5
+    else:
+        p, _, pert = I.config_3d(n=8)
+        p = dict(p, n=(40, 12, 45), periodic=(periodic[0], periodic[1], 0), V=0.6, z0=14 * 0.8)
+        steps, nshift = 90, 2
+    p = dict(p, **EQ12, **extra)
+    f = [a.ravel() for a in I.planar_front(dim, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
+    print(f"case: equal-potential {dim}D {p['n']} periodic={periodic} {extra} steps={steps}", flush=True)
+    h, t, g = _run_gpu(torch_dev, p, f, steps)
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert ref[3] == nshift
+    assert_parity(g, ref[:3], what=f"equal {dim}D")
+    _split_ok(p["ke"], g[1], g[2])
+    from paper_2303_09671_amd import pf
+    E = pf.pf_energy(h)[0]
+    assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_closed_runs_conserve_the_mixture(torch_dev, oracle, dim):
+    if dim == 1:
+        p, _ = I.config_1d(N=300)
+        p = dict(p, z0=120 * I.DX)
+    elif dim == 2:
+        p, _, _ = I.config_2d(nx=70, nz=60)
+        p = dict(p, z0=24 * I.DX)
+    else:
+        p, _, _ = I.config_3d(n=8)
+        p = dict(p, n=(36, 10, 40), z0=16 * I.DX)
+    p = dict(p, **EQ12, V=0.0, inv_lT=0.0)
+    phi, cs, cl = (a.ravel() for a in I.planar_front(dim, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=4))
+    cl = 1.3 * cl
+    cs = p["ke"] * cl
+    print(f"case: equal-potential conservation {dim}D", flush=True)
+    from paper_2303_09671_amd import pf
+    t = [_dev(torch_dev, a) for a in (phi, cs, cl)]
+    h = pf.pf_create(p, *t)
+    t0 = pf.pf_solute(h)[0][0]
+    pf.pf_step(h, 300)
+    t1 = pf.pf_solute(h)[0][0]
+    assert abs(t1 - t0) <= 1e-12 * abs(t0)
+    assert float((t[0].cpu() - torch_dev.from_numpy(phi)).abs().max()) > 1e-3
+
+
+def test_model_errors(torch_dev):
+    from paper_2303_09671_amd import pf
+    p, _ = I.config_1d(N=64)
+    p = dict(p, z0=16 * I.DX)
+    f = [_dev(torch_dev, a) for a in I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])]
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_create(dict(p, model=2), *f)
+    assert e.value.code == pf.PF_EINVAL
+    h = pf.pf_create(dict(p, model=1), *f)
+    lam = [torch_dev.zeros_like(x) for x in f]
+    lam2 = [torch_dev.zeros_like(x) for x in f]
+    dth = torch_dev.zeros(3, dtype=torch_dev.float64, device="cuda")
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_adjoint_step(h, 0, f, lam, lam2, dth)
+    assert e.value.code == pf.PF_EINVAL
