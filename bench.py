@@ -233,7 +233,7 @@ def main():
     k_avg = kern / args.steps
     achieved = BYTES_PER_CELL * cells / k_avg / 1e9
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=traffic_entry(), kernel="k_stream<3,32,8,APZ>", kernel_avg_us=k_avg * 1e6,
+                traffic=traffic_entry(), kernel="k_stream<3,32,8,APZ,EQ=false>", kernel_avg_us=k_avg * 1e6,
                 algorithmic_bytes_per_launch=BYTES_PER_CELL * cells)
     out = {
         "metric": "FP64 cell-updates/s and % HBM roofline; adjoint/forward step time ratio",

@@ -191,11 +191,12 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       double p, q, dp;
       pfk::interp<APZ>(c, su[0][i], p, q, dp);
       const double G = gph[0] * gph[0], dot = (c.Ds * gcs[0] - c.b * gcl[0]) * gph[0];
-      pt = pfk::cell_rate(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], sdm[i], p, q, dp, G, dot, c.W2 * lap,
-                          c.eps2, c.onemA);
+      const double kcl = (c.ke - 1.0) * cleq_of_lz(lz);
+      pt = pfk::cell_rate(c, kcl, su[0][i], su[1][i], su[2][i], sdm[i], p, q, dp, G, dot, c.W2 * lap, c.eps2, c.onemA);
     } else {
       double mu;
-      pfk::cell_stage<DIM, APZ>(c, cleq_of_lz(lz), su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
+      const double kcl = (c.ke - 1.0) * cleq_of_lz(lz);
+      pfk::cell_stage<DIM, APZ>(c, kcl, su[0][i], su[1][i], su[2][i], gph, gcs, gcl, lap, pt, mu);
     }
     spt[i] = pt;
   }

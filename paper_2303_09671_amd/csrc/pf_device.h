@@ -154,11 +154,11 @@ __device__ __forceinline__ double mubar_of(const Const& c, double phi, double cs
 // Wlap is W^2 lap.
 // phi_t from the interpolation values p, q = 1-p, p', dmu = (mu_s - mu_l)/Omega
 // and the scaled G, dot (see cell_core).
-__device__ __forceinline__ double cell_rate(const Const& c, double cleq, double phi, double cs, double cl, double dmu,
+__device__ __forceinline__ double cell_rate(const Const& c, double kcl, double phi, double cs, double cl, double dmu,
                                            double p, double q, double dp, double G, double dot, double Wlap,
                                            double eps2x, double onemAx) {
   const double dc = cs - cl;
-  const double dGc = cs * dmu + (c.ke - 1.0) * cleq - dc;  // Eq. dil5.2 with Eq. ds3
+  const double dGc = cs * dmu + kcl - dc;  // Eq. dil5.2 with Eq. ds3, kcl = (k_e - 1) c_l^eq
   const double ms = c.Ds * cs * q;                          // M_s (1 - p)
   const double ml = c.b * cl * p;                           // b M_l p
   const double Mb = ms + ml;
@@ -177,7 +177,7 @@ __device__ __forceinline__ double cell_rate(const Const& c, double cleq, double 
 
 // EQ: the equal-potential model (mu_s = mu_l = ln c_l imposed): dmu = 0.
 template <bool APZ, bool EQ = false>
-__device__ __forceinline__ void cell_core(const Const& c, double cleq, double phi, double cs, double cl, double G,
+__device__ __forceinline__ void cell_core(const Const& c, double kcl, double phi, double cs, double cl, double G,
                                           double dot, double Wlap, double eps2x, double onemAx, double& phit,
                                           double& mubar) {
   double p, q, dp;
@@ -185,13 +185,13 @@ __device__ __forceinline__ void cell_core(const Const& c, double cleq, double ph
   const double ll = flog(cl);
   const double dmu = EQ ? 0.0 : flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
   mubar = ll + p * dmu;
-  phit = cell_rate(c, cleq, phi, cs, cl, dmu, p, q, dp, G, dot, Wlap, eps2x, onemAx);
+  phit = cell_rate(c, kcl, phi, cs, cl, dmu, p, q, dp, G, dot, Wlap, eps2x, onemAx);
 }
 
 // g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
 // compact Laplacian of phi.
 template <int DIM, bool APZ = false, bool EQ = false>
-__device__ __forceinline__ void cell_stage(const Const& c, double cleq, double phi, double cs, double cl,
+__device__ __forceinline__ void cell_stage(const Const& c, double kcl, double phi, double cs, double cl,
                                            const double* gph, const double* gcs, const double* gcl,
                                            double lap, double& phit, double& mubar) {
   double G = 0.0, dot = 0.0;
@@ -200,13 +200,13 @@ __device__ __forceinline__ void cell_stage(const Const& c, double cleq, double p
     G += gph[k] * gph[k];
     dot += (c.Ds * gcs[k] - c.b * gcl[k]) * gph[k];
   }
-  cell_core<APZ, EQ>(c, cleq, phi, cs, cl, G, dot, c.W2 * lap, c.eps2, c.onemA, phit, mubar);
+  cell_core<APZ, EQ>(c, kcl, phi, cs, cl, G, dot, c.W2 * lap, c.eps2, c.onemA, phit, mubar);
 }
 
 // The same from plain differences: d*[k] = u_{+k} - u_{-k} and lsum the sum over
 // axes of u_{+k} - 2 u + u_{-k} (k = 1 / (4 dx^2)).
 template <int DIM, bool APZ = false, bool EQ = false>
-__device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, double phi, double cs, double cl,
+__device__ __forceinline__ void cell_stage_raw(const Const& c, double kcl, double phi, double cs, double cl,
                                                const double* dph, const double* dcs, const double* dcl,
                                                double lsum, double& phit, double& mubar) {
   double G = 0.0, dot = 0.0;
@@ -215,7 +215,7 @@ __device__ __forceinline__ void cell_stage_raw(const Const& c, double cleq, doub
     G += dph[k] * dph[k];
     dot += (c.Ds * dcs[k] - c.b * dcl[k]) * dph[k];
   }
-  cell_core<APZ, EQ>(c, cleq, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
+  cell_core<APZ, EQ>(c, kcl, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)

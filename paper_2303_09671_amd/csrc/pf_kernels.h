@@ -166,11 +166,14 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   // and gz-1 are in the ring; the plane above comes from the ring when
   // up_in_ring, else from global memory (it is loaded into the ring later).
   // Likewise the plane below comes from global memory when dn_global.
+  // (k_e - 1) c_l^eq of plane gz is affine in gz (frozen temperature, Eq. ds1):
+  // kq0 + kq1 gz, two scalars instead of the constants of the profile.
+  const double kq0 = (c.ke - 1.0) * cleq_at(c, (s_n + 0.5) * c.dx, t_n, c.V, c.z0);
+  const double kq1 = (1.0 - c.ke) * (1.0 - c.ke) * c.dx * c.inv_lT * c.inv_ke;
   auto cell_plane = [&](int gz, bool up_in_ring, bool dn_global) {
     const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
     const int pt = (gz + 8) & 1, mu = (gz + 9) % 3;
-    const double zlab = ((double)gz + s_n + 0.5) * c.dx;
-    const double cleq = cleq_at(c, zlab, t_n, c.V, c.z0);
+    const double kcl = __builtin_fma(kq1, (double)gz, kq0);
     const long long zup = plane * mirror_idx(gz + 1, nz);
     const long long zdn = plane * mirror_idx(gz - 1, nz);
 #pragma unroll
@@ -220,7 +223,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       gcl[DIM - 1] = upL - dnL;
       lap += (upP - 2.0 * ph + dnP);
       double phit, mubar;
-      cell_stage_raw<DIM, APZ, EQ>(c, cleq, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
+      cell_stage_raw<DIM, APZ, EQ>(c, kcl, ph, cs, cl, gph, gcs, gcl, lap, phit, mubar);
       spt[pt][i] = phit;
       smu[mu][i] = mubar;
     }
@@ -579,8 +582,8 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
         double gcl1[1] = {lp - lm};
         const double lap = pp - 2.0 * P[k] + pm;
         const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
-        const double cleq = cleq_at(c, zlab, tn, V, z0);
-        cell_stage_raw<1, APZ, EQ>(c, cleq, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
+        const double kcl = (c.ke - 1.0) * cleq_at(c, zlab, tn, V, z0);
+        cell_stage_raw<1, APZ, EQ>(c, kcl, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
       }
     }
     // exchange 2: phi_t and mu_bar of the chunk edges

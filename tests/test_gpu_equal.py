@@ -4,7 +4,8 @@ KKS for A = 1 and b = k_e D_s/D_l) against the CPU oracle, through the C ABI.
 Same bar as the separate-kinetics step: max relative field error <= 1e-10
 per field after the whole run.  Cases: the KKS special case and A = 1.2 in 1D,
 uneven batched runs (1..8 cells per thread), 2D and 3D grids with ragged tiles,
-mirror and periodic transverse axes and window shifts, and a nonzero a_p.  Also:
+mirror and periodic transverse axes and window shifts, and a nonzero a_p, and one
+step at the full 2D and 3D workload sizes.  Also:
 the split c_s = k_e c_l holds on the GPU output, closed runs conserve the
 mixture, and the adjoint entry points refuse model 1.
 """
@@ -148,3 +149,26 @@ def test_model_errors(torch_dev):
     with pytest.raises(pf.PFError) as e:
         pf.pf_adjoint_step(h, 0, f, lam, lam2, dth)
     assert e.value.code == pf.PF_EINVAL
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+def test_full_size_one_step(torch_dev, oracle, which):
+    """Workload sizes as configured (2D 1024^2, 3D 256^3) in the benchmark's
+    launch configuration: 40 GPU steps, then one more GPU step against one
+    oracle step from the GPU's state, on every cell."""
+    if which == "2d":
+        p, _, pert = I.config_2d()
+    else:
+        p, _, pert = I.config_3d()
+    p = dict(p, **EQ12)
+    f = [a.ravel() for a in I.planar_front(p["dim"], p["n"], p["dx"], p["z0"], p["ke"], amp=pert["amp"],
+                                           seed=pert["seed"])]
+    print(f"case: equal-potential full-size {which} one step", flush=True)
+    from paper_2303_09671_amd import pf
+    h, t, g40 = _run_gpu(torch_dev, p, f, 40)
+    pf.pf_step(h, 1)
+    torch_dev.cuda.synchronize()
+    g41 = [x.cpu().numpy() for x in t]
+    s40 = int(np.floor(p["V"] * (40 * p["dt"]) / p["dx"]))
+    ref = oracle.step(oracle_params(oracle, p), *g40, 1, n0=40, shift=s40)
+    assert_parity(g41, ref[:3], what=f"equal full-size {which}")
