@@ -44,7 +44,8 @@
 // Eq. solute_nonvar.  After each step the phase concentrations are recovered from
 // c and the new phi by the equal-potential condition of the dilute ideal alloy
 // (Eq. dil1: ln(c_s/k_e) = ln c_l), i.e. c_s = k_e c_l and
-// c_l = c / (k_e p + 1 - p).
+// c_l = c / (k_e p + 1 - p).  The state of this model is (phi, c_l): c_s on input
+// is replaced by k_e c_l.
 //
 // The step is templated on the scalar type so that the same code also runs on
 // dual numbers, which gives exact forward-mode directional derivatives (JVPs)
@@ -394,6 +395,8 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
   const long N = g.ncell;
   const int gz = P.dim - 1;
   const double t = (double)n * P.dt;
+  if (P.model == 1)  // c_s is not a state variable of this model: it follows c_l
+    for (long i = 0; i < N; ++i) cs[i] = P.ke * cl[i];
   StepWork<T> S;
   S.phit.assign(N, T(0.0));
   S.mubar.assign(N, T(0.0));
