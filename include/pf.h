@@ -81,7 +81,8 @@ typedef struct pf_params {
                          *    c = p c_s + (1-p) c_l conserved with the flux of Eq.
                          *    solute_nonvar, and after every step c_l = c / (k_e p + 1 - p),
                          *    c_s = k_e c_l (Eq. dil1).  The fields keep the (phi, c_s, c_l)
-                         *    layout; the first step takes c from the fields as given.  The
+                         *    layout, but the state is (phi, c_l): c_s on input is not read
+                         *    (taken as k_e c_l) and is written after every step.  The
                          *    adjoint entry points return PF_EINVAL for model 1.           */
   const int32_t* run_n;    /* cells of run r (3 <= run_n[r] <= 8192)               */
   const int64_t* run_off;  /* first cell of run r in the field arrays              */

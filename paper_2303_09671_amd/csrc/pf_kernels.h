@@ -78,6 +78,12 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   __shared__ double smu[3][G::P1];
   __shared__ double sfx[2][G::NFX];
   __shared__ double sfy[2][(G::NFY > 0) ? G::NFY : 1];
+  // c_s at ring slot sl, position i.  The equal-potential model reads no c_s:
+  // its c_s is k_e c_l exactly, the value its update stores.
+  auto CS = [&](int sl, int i) -> double {
+    if constexpr (EQ) return c.ke * su[sl][2][i];
+    else return su[sl][1][i];
+  };
 
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX;
@@ -156,7 +162,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       if (i < G::P2) {
         const long long idx = ld_off[r] + zo;
         su[slot][0][i] = iph[idx];
-        su[slot][1][i] = ics[idx];
+        if constexpr (!EQ) su[slot][1][i] = ics[idx];
         su[slot][2][i] = icl[idx];
       }
     }
@@ -185,36 +191,35 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       double upP, upS, upL, dnP, dnS, dnL;
       if (up_in_ring) {
         upP = su[sp][0][ic];
-        upS = su[sp][1][ic];
+        upS = CS(sp, ic);
         upL = su[sp][2][ic];
       } else {
         const long long o = cs_off[r] + zup;
         upP = iph[o];
-        upS = ics[o];
         upL = icl[o];
+        upS = EQ ? c.ke * upL : ics[o];
       }
       if (dn_global) {
         const long long o = cs_off[r] + zdn;
         dnP = iph[o];
-        dnS = ics[o];
         dnL = icl[o];
+        dnS = EQ ? c.ke * dnL : ics[o];
       } else {
         dnP = su[sm][0][ic];
-        dnS = su[sm][1][ic];
+        dnS = CS(sm, ic);
         dnL = su[sm][2][ic];
       }
       double gph[DIM], gcs[DIM], gcl[DIM];
       const double* U0 = su[s0][0];
-      const double* S0 = su[s0][1];
       const double* L0 = su[s0][2];
-      const double ph = U0[ic], cs = S0[ic], cl = L0[ic];
+      const double ph = U0[ic], cs = CS(s0, ic), cl = L0[ic];
       gph[0] = U0[ic + 1] - U0[ic - 1];  // plain differences (cell_stage_raw)
-      gcs[0] = S0[ic + 1] - S0[ic - 1];
+      gcs[0] = CS(s0, ic + 1) - CS(s0, ic - 1);
       gcl[0] = L0[ic + 1] - L0[ic - 1];
       double lap = (U0[ic + 1] - 2.0 * ph + U0[ic - 1]);
       if (DIM == 3) {
         gph[1] = U0[ic + G::BX2] - U0[ic - G::BX2];
-        gcs[1] = S0[ic + G::BX2] - S0[ic - G::BX2];
+        gcs[1] = CS(s0, ic + G::BX2) - CS(s0, ic - G::BX2);
         gcl[1] = L0[ic + G::BX2] - L0[ic - G::BX2];
         lap += (U0[ic + G::BX2] - 2.0 * ph + U0[ic - G::BX2]);
       }
@@ -242,7 +247,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
     double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
     const double pa_ = su[sa][0][ic], pb_ = su[sb][0][ic];
-    const double ca = su[sa][1][ic], cb = su[sb][1][ic];
+    const double ca = CS(sa, ic), cb = CS(sb, ic);
     const double la = su[sa][2][ic], lb = su[sb][2][ic];
     const int k = DIM - 1;
     gph[k] = pb_ - pa_;  // dx-scaled face stage: plain differences and sums of them
@@ -252,14 +257,14 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     {  // x
       gph[0] = (su[sa][0][ic + 1] - su[sa][0][ic - 1]) + (su[sb][0][ic + 1] - su[sb][0][ic - 1]);
       gmu[0] = (smu[ma][i1 + 1] - smu[ma][i1 - 1]) + (smu[mb][i1 + 1] - smu[mb][i1 - 1]);
-      gcs[0] = (su[sa][1][ic + 1] - su[sa][1][ic - 1]) + (su[sb][1][ic + 1] - su[sb][1][ic - 1]);
+      gcs[0] = (CS(sa, ic + 1) - CS(sa, ic - 1)) + (CS(sb, ic + 1) - CS(sb, ic - 1));
       gcl[0] = (su[sa][2][ic + 1] - su[sa][2][ic - 1]) + (su[sb][2][ic + 1] - su[sb][2][ic - 1]);
     }
     if (DIM == 3) {
       const int d2 = G::BX2, d1 = G::BX1;
       gph[1] = (su[sa][0][ic + d2] - su[sa][0][ic - d2]) + (su[sb][0][ic + d2] - su[sb][0][ic - d2]);
       gmu[1] = (smu[ma][i1 + d1] - smu[ma][i1 - d1]) + (smu[mb][i1 + d1] - smu[mb][i1 - d1]);
-      gcs[1] = (su[sa][1][ic + d2] - su[sa][1][ic - d2]) + (su[sb][1][ic + d2] - su[sb][1][ic - d2]);
+      gcs[1] = (CS(sa, ic + d2) - CS(sa, ic - d2)) + (CS(sb, ic + d2) - CS(sb, ic - d2));
       gcl[1] = (su[sa][2][ic + d2] - su[sa][2][ic - d2]) + (su[sb][2][ic + d2] - su[sb][2][ic - d2]);
     }
     const double ptf = 0.5 * (spt[pa][i1] + spt[pb][i1]);
@@ -293,7 +298,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int ja = G::i1(ax, ay), jb = G::i1(bx, by);
     double gph[DIM], gmu[DIM], gcs[DIM], gcl[DIM];
     const double pa = su[s0][0][ia], pb = su[s0][0][ib];
-    const double ca = su[s0][1][ia], cb = su[s0][1][ib];
+    const double ca = CS(s0, ia), cb = CS(s0, ib);
     const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
     gph[K] = pb - pa;  // dx-scaled face stage: plain differences and sums of them
     gmu[K] = smu[m0][jb] - smu[m0][ja];
@@ -305,13 +310,13 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       constexpr int d1 = (J == 0) ? 1 : G::BX1;
       gph[J] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
       gmu[J] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
-      gcs[J] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
+      gcs[J] = (CS(s0, ia + d2) - CS(s0, ia - d2)) + (CS(s0, ib + d2) - CS(s0, ib - d2));
       gcl[J] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
     }
     constexpr int kz = DIM - 1;  // transverse z
     gph[kz] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
     gmu[kz] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
-    gcs[kz] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
+    gcs[kz] = (CS(sp, ia) - CS(sm, ia)) + (CS(sp, ib) - CS(sm, ib));
     gcl[kz] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
     const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
     double Fs, Fl;
@@ -345,7 +350,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int d2 = (K == 0) ? G::BX2 : 1, d1 = (K == 0) ? G::BX1 : 1;  // the other in-plane axis
     double gph[3], gmu[3], gcs[3], gcl[3];
     const double pa = su[s0][0][ia], pb = su[s0][0][ib];
-    const double ca = su[s0][1][ia], cb = su[s0][1][ib];
+    const double ca = CS(s0, ia), cb = CS(s0, ib);
     const double la_ = su[s0][2][ia], lb_ = su[s0][2][ib];
     gph[0] = pb - pa;
     gmu[0] = smu[m0][jb] - smu[m0][ja];
@@ -353,11 +358,11 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     gcl[0] = lb_ - la_;
     gph[1] = (su[s0][0][ia + d2] - su[s0][0][ia - d2]) + (su[s0][0][ib + d2] - su[s0][0][ib - d2]);
     gmu[1] = (smu[m0][ja + d1] - smu[m0][ja - d1]) + (smu[m0][jb + d1] - smu[m0][jb - d1]);
-    gcs[1] = (su[s0][1][ia + d2] - su[s0][1][ia - d2]) + (su[s0][1][ib + d2] - su[s0][1][ib - d2]);
+    gcs[1] = (CS(s0, ia + d2) - CS(s0, ia - d2)) + (CS(s0, ib + d2) - CS(s0, ib - d2));
     gcl[1] = (su[s0][2][ia + d2] - su[s0][2][ia - d2]) + (su[s0][2][ib + d2] - su[s0][2][ib - d2]);
     gph[2] = (su[sp][0][ia] - su[sm][0][ia]) + (su[sp][0][ib] - su[sm][0][ib]);
     gmu[2] = (smu[mp][ja] - smu[mm][ja]) + (smu[mp][jb] - smu[mm][jb]);
-    gcs[2] = (su[sp][1][ia] - su[sm][1][ia]) + (su[sp][1][ib] - su[sm][1][ib]);
+    gcs[2] = (CS(sp, ia) - CS(sm, ia)) + (CS(sp, ib) - CS(sm, ib));
     gcl[2] = (su[sp][2][ia] - su[sm][2][ia]) + (su[sp][2][ib] - su[sm][2][ib]);
     const double ptf = 0.5 * (spt[pt][ja] + spt[pt][jb]);
     double Fs, Fl;
@@ -410,7 +415,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     if (own_valid) {
       const int s0 = slot3(z);
       const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
-      const double ph = su[s0][0][ic], cs = su[s0][1][ic], cl = su[s0][2][ic];
+      const double ph = su[s0][0][ic], cs = CS(s0, ic), cl = su[s0][2][ic];
       const double pt = spt[(z + 8) & 1][i1];
       double divs = sfx[0][oy * (TX + 1) + ox + 1] - sfx[0][oy * (TX + 1) + ox];
       if (DIM == 3) divs += sfy[0][(oy + 1) * TX + ox] - sfy[0][oy * TX + ox];
@@ -513,8 +518,8 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
   for (int k = 0; k < CM; ++k) {
     if (k < cnt) {
       P[k] = gph[off + i0 + k];
-      S[k] = gcs[off + i0 + k];
       L[k] = gcl[off + i0 + k];
+      S[k] = EQ ? c.ke * L[k] : gcs[off + i0 + k];  // equal potentials: c_s = k_e c_l
     } else {
       P[k] = 0.0;
       S[k] = 1.0;

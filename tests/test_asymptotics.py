@@ -202,3 +202,14 @@ def test_table1_unit_map():
     assert abs(s["lambda0"] - asy.I_DW * 0.3 / 0.49) < 1e-15  # W = d0
     n = asy.nondim("Ni-5Cu", 26e-9, 1.0)
     assert abs(n["dT0"] - 10.0) < 1e-12 and abs(n["V"] - 26e-9 / 3e-9) < 1e-12
+
+
+def test_band_workload_matches_table1_map():
+    """The solute-band workload is the Table 1 alloy Si-9%As at W = 13.5 nm,
+    v_p = 0.3 m/s and G = 1.4e6 K/m mapped to the library's units."""
+    from paper_2303_09671_amd import inputs as I
+    p, _ = I.config_bands()
+    s = asy.nondim("Si-9As", 13.5e-9, 0.3, G=1.4e6)
+    assert abs(p["V"] - s["V"]) < 1e-12 and p["ke"] == s["ke"]
+    assert abs(p["inv_lT"] - s["inv_lT"]) < 1e-3 * s["inv_lT"]  # l_T rounded to 4444 W
+    assert abs(p["lambda0"] - s["lambda0"]) < 1e-15

@@ -172,3 +172,30 @@ def test_full_size_one_step(torch_dev, oracle, which):
     s40 = int(np.floor(p["V"] * (40 * p["dt"]) / p["dx"]))
     ref = oracle.step(oracle_params(oracle, p), *g40, 1, n0=40, shift=s40)
     assert_parity(g41, ref[:3], what=f"equal full-size {which}")
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_input_cs_is_not_read(torch_dev, oracle, dim):
+    """The state of the equal-potential model is (phi, c_l): an input c_s off the
+    split gives bit for bit the run of c_s = k_e c_l, and the oracle agrees."""
+    if dim == 1:
+        p, _ = I.config_1d(N=300)
+        p = dict(p, z0=75 * I.DX)
+    elif dim == 2:
+        p, _, _ = I.config_2d(nx=70, nz=48)
+        p = dict(p, V=0.5, z0=14 * I.DX)
+    else:
+        p, _, _ = I.config_3d(n=8)
+        p = dict(p, n=(36, 10, 40), V=0.6, z0=14 * I.DX)
+    p = dict(p, **EQ12)
+    phi, cs, cl = (a.ravel() for a in I.planar_front(dim, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=6))
+    rng = np.random.default_rng(1)
+    cs_off = 0.05 + rng.random(cs.size)
+    steps = 60
+    print(f"case: equal-potential input c_s ignored {dim}D", flush=True)
+    _, _, g1 = _run_gpu(torch_dev, p, (phi, cs_off, cl), steps)
+    _, _, g2 = _run_gpu(torch_dev, p, (phi, p["ke"] * cl, cl), steps)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+    ref = oracle.step(oracle_params(oracle, p), phi, cs_off, cl, steps)
+    assert_parity(g1, ref[:3], what=f"equal input c_s {dim}D")
