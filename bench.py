@@ -178,12 +178,33 @@ def cpu_baseline(p, pert):
     f = [a.ravel() for a in I.planar_front(p["dim"], p["n"], p["dx"], p["z0"], p["ke"], amp=pert["amp"],
                                            seed=pert["seed"])]
     cells = int(np.prod([p["n"][k] for k in range(p["dim"])]))
+    grid = "x".join(str(v) for v in p["n"][:p["dim"]])
     t0 = time.perf_counter()
     O.step(po, *f, 1)
     dt = time.perf_counter() - t0
-    return dict(value=cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"one step of the full {'x'.join(str(v) for v in p['n'][:p['dim']])} grid "
-                       f"({cells} cell-updates, {dt:.1f} s, single thread)")
+    out = dict(value=cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
+               sample=f"one step of the full {grid} grid ({cells} cell-updates, {dt:.1f} s, single thread)")
+    # the same oracle source built with its OpenMP cell loops, on all host cores
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    O.step(po, *f, 1, openmp=True)  # thread-pool start-up outside the timed region
+    t0 = time.perf_counter()
+    O.step(po, *f, 2, openmp=True)
+    dt2 = time.perf_counter() - t0
+    out["all_cores"] = dict(value=2 * cells / dt2, unit="cell-updates/s", cores=threads, nproc=os.cpu_count(),
+                            cpu=_cpu_model(), kind="oracle (OpenMP cell loops, bit-identical results)",
+                            sample=f"two steps of the full {grid} grid ({dt2:.1f} s)")
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def traffic_entry():

@@ -14,13 +14,20 @@ SRC = os.path.join(HERE, "pf_oracle.cpp")
 OUT = os.path.join(HERE, "liborc.so")
 
 
+OUT_OMP = os.path.join(HERE, "liborc_omp.so")
+
+
 def build(verbose: bool = False) -> str:
-    cmd = ["g++", "-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", OUT + ".tmp", SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
+    """liborc.so (single thread) and liborc_omp.so (the same source with its
+    OpenMP cell loops enabled, used only to time the oracle on all host cores)."""
+    base = ["g++", "-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+            "-Wextra"]
+    for out, extra in ((OUT, ["-Wno-unknown-pragmas"]), (OUT_OMP, ["-fopenmp"])):
+        cmd = base + extra + ["-o", out + ".tmp", SRC]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return OUT
 
 

@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liborc.so")
+LIB_OMP_PATH = os.path.join(_HERE, "liborc_omp.so")
 
 #: Default nondimensional parameters (lengths in W0, time in W0^2/D_l, c in c_inf).
 DEFAULTS = dict(
@@ -47,36 +48,47 @@ class _Params(C.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    """Load the oracle shared library (raises if it has not been built)."""
-    global _lib
+def lib(openmp: bool = False):
+    """Load the oracle shared library (raises if it has not been built).
+    openmp=True loads the build with OpenMP cell loops (same source and
+    results; used only to time the oracle on all host cores)."""
+    global _lib, _lib_omp
+    if openmp:
+        if _lib_omp is None:
+            _lib_omp = _load(LIB_OMP_PATH)
+        return _lib_omp
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"oracle library missing: {LIB_PATH} (run oracle/build.py)")
-        L = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        L.orc_params_size.restype = C.c_int
-        L.orc_step.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_long, C.POINTER(C.c_int64)]
-        L.orc_step.restype = C.c_int
-        L.orc_jvp.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, dp, dp, C.c_long, C.c_long,
-                              C.POINTER(C.c_int64)]
-        L.orc_jvp.restype = C.c_int
-        L.orc_energy.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64]
-        L.orc_energy.restype = C.c_double
-        L.orc_solute.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
-        L.orc_solute.restype = C.c_int
-        L.orc_pointwise.argtypes = [C.POINTER(_Params), C.c_double, C.c_double, C.c_double, C.c_double, dp]
-        L.orc_pointwise.restype = C.c_int
-        L.orc_phi_t.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64, dp]
-        L.orc_phi_t.restype = C.c_int
-        L.orc_front.argtypes = [C.POINTER(_Params), dp, C.c_long, C.c_int64, dp]
-        L.orc_front.restype = C.c_int
-        if L.orc_params_size() != C.sizeof(_Params):
-            raise RuntimeError("oracle parameter layout mismatch")
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def _load(path):
+    if not os.path.exists(path):
+        raise RuntimeError(f"oracle library missing: {path} (run oracle/build.py)")
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_params_size.restype = C.c_int
+    L.orc_step.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_long, C.POINTER(C.c_int64)]
+    L.orc_step.restype = C.c_int
+    L.orc_jvp.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, dp, dp, C.c_long, C.c_long,
+                          C.POINTER(C.c_int64)]
+    L.orc_jvp.restype = C.c_int
+    L.orc_energy.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64]
+    L.orc_energy.restype = C.c_double
+    L.orc_solute.argtypes = [C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
+    L.orc_solute.restype = C.c_int
+    L.orc_pointwise.argtypes = [C.POINTER(_Params), C.c_double, C.c_double, C.c_double, C.c_double, dp]
+    L.orc_pointwise.restype = C.c_int
+    L.orc_phi_t.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64, dp]
+    L.orc_phi_t.restype = C.c_int
+    L.orc_front.argtypes = [C.POINTER(_Params), dp, C.c_long, C.c_int64, dp]
+    L.orc_front.restype = C.c_int
+    if L.orc_params_size() != C.sizeof(_Params):
+        raise RuntimeError("oracle parameter layout mismatch")
+    return L
 
 
 def params(**kw) -> dict:
@@ -126,13 +138,14 @@ def _fields(phi, cs, cl, p):
     return out
 
 
-def step(p: dict, phi, cs, cl, nsteps: int, n0: int = 0, shift: int = 0):
+def step(p: dict, phi, cs, cl, nsteps: int, n0: int = 0, shift: int = 0, openmp: bool = False):
     """Advance copies of the fields by ``nsteps`` steps from step index ``n0``.
 
-    Returns ``(phi, cs, cl, shift)`` with ``shift`` the updated window count."""
+    Returns ``(phi, cs, cl, shift)`` with ``shift`` the updated window count.
+    openmp=True runs the same steps on all host cores (OMP_NUM_THREADS)."""
     phi, cs, cl = _fields(phi, cs, cl, p)
     s = C.c_int64(int(shift))
-    rc = lib().orc_step(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n0), int(nsteps), C.byref(s))
+    rc = lib(openmp).orc_step(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n0), int(nsteps), C.byref(s))
     if rc != 0:
         raise RuntimeError("orc_step failed")
     return phi, cs, cl, int(s.value)

@@ -401,25 +401,32 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
   S.phit.assign(N, T(0.0));
   S.mubar.assign(N, T(0.0));
   S.pw.resize(N);
-  int c[3];
-  for (c[2] = 0; c[2] < g.n[2]; ++c[2])
-    for (c[1] = 0; c[1] < g.n[1]; ++c[1])
-      for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
+  // The cell loops carry OpenMP pragmas for the all-cores timing build: every
+  // cell is independent, so the result does not depend on the thread count.
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int c2 = 0; c2 < g.n[2]; ++c2)
+    for (int c1 = 0; c1 < g.n[1]; ++c1)
+      for (int c0 = 0; c0 < g.n[0]; ++c0) {
+        const int c[3] = {c0, c1, c2};
         long i = g.lin(c);
         double zlab = ((double)c[gz] + (double)(*s_shift) + 0.5) * P.dx;
         S.pw[i] = pointwise(P, w, phi[i], cs[i], cl[i], cleq_of(P, zlab, t));
         S.mubar[i] = S.pw[i].mubar;
       }
-  for (c[2] = 0; c[2] < g.n[2]; ++c[2])
-    for (c[1] = 0; c[1] < g.n[1]; ++c[1])
-      for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int c2 = 0; c2 < g.n[2]; ++c2)
+    for (int c1 = 0; c1 < g.n[1]; ++c1)
+      for (int c0 = 0; c0 < g.n[0]; ++c0) {
+        const int c[3] = {c0, c1, c2};
         long i = g.lin(c);
         S.phit[i] = phi_t_at(P, w, g, phi, cs, cl, S.pw[i], c);
       }
   std::vector<T> nphi(N), ncs(N), ncl(N);
-  for (c[2] = 0; c[2] < g.n[2]; ++c[2])
-    for (c[1] = 0; c[1] < g.n[1]; ++c[1])
-      for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int c2 = 0; c2 < g.n[2]; ++c2)
+    for (int c1 = 0; c1 < g.n[1]; ++c1)
+      for (int c0 = 0; c0 < g.n[0]; ++c0) {
+        const int c[3] = {c0, c1, c2};
         long i = g.lin(c);
         T divs = 0.0, divl = 0.0;
         for (int k = 0; k < P.dim && P.model == 0; ++k) {
@@ -469,6 +476,7 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
   const double tn1 = (double)(n + 1) * P.dt;
   bool shift = std::floor(P.V * tn1 / P.dx) > (double)(*s_shift);
   if (shift) {
+    int c[3];
     for (c[2] = 0; c[2] < g.n[2]; ++c[2])
       for (c[1] = 0; c[1] < g.n[1]; ++c[1])
         for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
