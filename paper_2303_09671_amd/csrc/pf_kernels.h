@@ -572,31 +572,39 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
       rS = pick(S, cnt - 1);
       rL = pick(L, cnt - 1);
     }
-    // cell stage
-    double PT[CM], MU[CM];
+    // Cell stage of local cell k (a constant once the loops are unrolled) from
+    // the old values of the cell and its neighbours; the chunk ends take their
+    // outer neighbours from exchange 1.
+    auto cell = [&](int k, double& pt, double& mu) {
+      const double pm = (k == 0) ? lP : P[(k > 0) ? k - 1 : 0], pp = (k == cnt - 1) ? rP : P[(k + 1 < CM) ? k + 1 : k];
+      const double sm = (k == 0) ? lS : S[(k > 0) ? k - 1 : 0], sp = (k == cnt - 1) ? rS : S[(k + 1 < CM) ? k + 1 : k];
+      const double lm = (k == 0) ? lL : L[(k > 0) ? k - 1 : 0], lp = (k == cnt - 1) ? rL : L[(k + 1 < CM) ? k + 1 : k];
+      double gph1[1] = {pp - pm};  // plain differences (cell_stage_raw)
+      double gcs1[1] = {sp - sm};
+      double gcl1[1] = {lp - lm};
+      const double lap = pp - 2.0 * P[k] + pm;
+      const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
+      const double kcl = (c.ke - 1.0) * cleq_at(c, zlab, tn, V, z0);
+      cell_stage_raw<1, APZ, EQ>(c, kcl, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, pt, mu);
+    };
+    // phi_t and mu_bar of the chunk's first and last cells first: they go to the
+    // neighbours; the others are computed as the face loop reaches them, so only
+    // a few of them are live at a time
+    double PT0 = 0.0, MU0 = 0.0, PTl = 0.0, MUl = 0.0;
+    if (cnt > 0) cell(0, PT0, MU0);
 #pragma unroll
-    for (int k = 0; k < CM; ++k) {
-      PT[k] = 0.0;
-      MU[k] = 0.0;
-      if (k < cnt) {
-        const double pm = (k == 0) ? lP : P[k - 1], pp = (k == cnt - 1) ? rP : P[(k + 1 < CM) ? k + 1 : k];
-        const double sm = (k == 0) ? lS : S[k - 1], sp = (k == cnt - 1) ? rS : S[(k + 1 < CM) ? k + 1 : k];
-        const double lm = (k == 0) ? lL : L[k - 1], lp = (k == cnt - 1) ? rL : L[(k + 1 < CM) ? k + 1 : k];
-        double gph1[1] = {pp - pm};  // plain differences (cell_stage_raw)
-        double gcs1[1] = {sp - sm};
-        double gcl1[1] = {lp - lm};
-        const double lap = pp - 2.0 * P[k] + pm;
-        const double zlab = ((double)(i0 + k) + sn + 0.5) * c.dx;
-        const double kcl = (c.ke - 1.0) * cleq_at(c, zlab, tn, V, z0);
-        cell_stage_raw<1, APZ, EQ>(c, kcl, P[k], S[k], L[k], gph1, gcs1, gcl1, lap, PT[k], MU[k]);
-      }
+    for (int k = 1; k < CM; ++k)
+      if (k == cnt - 1) cell(k, PTl, MUl);
+    if (cnt == 1) {
+      PTl = PT0;
+      MUl = MU0;
     }
     // exchange 2: phi_t and mu_bar of the chunk edges
     if (cnt > 0) {
-      xd[0][0][t] = PT[0];
-      xd[0][1][t] = MU[0];
-      xd[1][0][t] = pick(PT, cnt - 1);
-      xd[1][1][t] = pick(MU, cnt - 1);
+      xd[0][0][t] = PT0;
+      xd[0][1][t] = MU0;
+      xd[1][0][t] = PTl;
+      xd[1][1][t] = MUl;
     }
     __syncthreads();
     const double lPT = at_lo ? 0.0 : xd[1][0][t - 1];
@@ -604,31 +612,13 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
     const double rPT = has_right ? xd[0][0][t + 1] : 0.0;
     const double rMU = has_right ? xd[0][1][t + 1] : 0.0;
     // Faces j = 0..cnt lie between local cells j-1 and j (mirror ends have zero
-    // flux).  Rolling over the cells: face j+1 is computed before cell j is
+    // flux).  Rolling over the cells: face k+1 is computed before cell k is
     // updated, so no face array is kept.
-    auto face = [&](int j, double& Fs, double& Fl) {
+    auto face = [&](bool none, double pa, double sa, double la, double ta, double ma, double pb, double sb,
+                    double lb, double tb, double mb, double& Fs, double& Fl) {
       Fs = 0.0;
       Fl = 0.0;
-      if (cnt <= 0 || (j == 0 && at_lo) || (j == cnt && at_hi)) return;
-      double pa = lP, sa = lS, la = lL, ta = lPT, ma = lMU;
-      double pb = rP, sb = rS, lb = rL, tb = rPT, mb = rMU;
-#pragma unroll
-      for (int k = 0; k < CM; ++k) {
-        if (k == j - 1) {
-          pa = P[k];
-          sa = S[k];
-          la = L[k];
-          ta = PT[k];
-          ma = MU[k];
-        }
-        if (k == j && j < cnt) {
-          pb = P[k];
-          sb = S[k];
-          lb = L[k];
-          tb = PT[k];
-          mb = MU[k];
-        }
-      }
+      if (none) return;
       double g0[1] = {pb - pa};  // dx-scaled face stage: plain differences
       double g1[1] = {mb - ma};
       double g2[1] = {sb - sa};
@@ -637,14 +627,34 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
                                Fs, Fl);
     };
     double FsL, FlL;
-    face(0, FsL, FlL);
+    face(cnt <= 0 || at_lo, lP, lS, lL, lPT, lMU, P[0], S[0], L[0], PT0, MU0, FsL, FlL);
+    double ptc = PT0, muc = MU0;  // phi_t and mu_bar of the current cell
 #pragma unroll
     for (int k = 0; k < CM; ++k) {
       if (k < cnt) {
+        const int k1 = (k + 1 < CM) ? k + 1 : k;  // in range; used only when k + 1 < cnt
+        double ptn, mun, pn, sn1, ln;  // the cell right of face k+1
+        if (k + 1 < cnt) {
+          if (k + 1 == cnt - 1) {
+            ptn = PTl;
+            mun = MUl;
+          } else {
+            cell(k1, ptn, mun);
+          }
+          pn = P[k1];
+          sn1 = S[k1];
+          ln = L[k1];
+        } else {
+          ptn = rPT;
+          mun = rMU;
+          pn = rP;
+          sn1 = rS;
+          ln = rL;
+        }
         double FsR, FlR;
-        face(k + 1, FsR, FlR);
+        face(k == cnt - 1 && at_hi, P[k], S[k], L[k], ptc, muc, pn, sn1, ln, ptn, mun, FsR, FlR);
         double ns, nl;
-        const double np_ = P[k] + dt * PT[k];
+        const double np_ = P[k] + dt * ptc;
         if constexpr (EQ) {  // conserved mixture, then the equal-potential split at the new phi
           double p, q;
           interp_pq<APZ>(c, P[k], p, q);
@@ -652,7 +662,7 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
         } else {
           double p, q, dp;
           interp<APZ>(c, P[k], p, q, dp);
-          const double src = -c.A * (S[k] - L[k]) * dp * PT[k];
+          const double src = -c.A * (S[k] - L[k]) * dp * ptc;
           ns = S[k] + dt * ((FsR - FsL) * c.inv_dx2 + src);
           nl = L[k] + dt * ((FlR - FlL) * c.inv_dx2 + src);
         }
@@ -662,6 +672,8 @@ __device__ __forceinline__ void run1d_body(const Const& c, const RunTab& rt, int
         errbits |= check_bits(P[k], S[k], L[k]);
         FsL = FsR;
         FlL = FlR;
+        ptc = ptn;
+        muc = mun;
       }
     }
     if (shift) {  // uniform across the workgroup
