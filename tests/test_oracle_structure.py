@@ -10,6 +10,8 @@
   of the step, for the fields and for theta = (A, M_phi, W).
 * The moving window: after a shift the fresh hot-end layer is (0, k_e, 1) and
   every other layer moved down by one cell (Sec. V.A shifting algorithm).
+* The OpenMP build used to time the oracle on all cores steps bit for bit like
+  the single-thread build.
 """
 import numpy as np
 import pytest
@@ -110,3 +112,26 @@ def test_window_shift(oracle):
     u = oracle.step(dict(P, V=P["V"] * 0.999), *a[:3], 1, n0=2, shift=0)  # no shift: floor(0.999) = 0
     assert u[3] == 0
     del Pn
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_openmp_build_is_bit_identical(oracle, model):
+    """The all-cores timing build (OpenMP cell loops) steps exactly as the
+    single-thread build: every cell is independent within a step."""
+    import os
+    P = oracle.params(dim=3, n=(12, 10, 16), periodic=(1, 0, 0), V=0.6, dt=0.03, z0=5 * 0.8, model=model,
+                      eps_grad=1e-4 if model else 1e-20)
+    phi, cs, cl = (a.ravel() for a in I.planar_front(3, P["n"], 0.8, P["z0"], P["ke"], amp=0.05, seed=3))
+    old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "4"
+    try:
+        a = oracle.step(P, phi, cs, cl, 80)
+        b = oracle.step(P, phi, cs, cl, 80, openmp=True)
+    finally:
+        if old is None:
+            os.environ.pop("OMP_NUM_THREADS")
+        else:
+            os.environ["OMP_NUM_THREADS"] = old
+    assert a[3] == b[3] and a[3] >= 1
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
