@@ -252,3 +252,33 @@ def test_batch_full_sweep_sampled(torch_dev, oracle):
             assert_parity(gr, ref, what=f"run {i} N={N} V={runs[i]['V']:.3g}")
         else:
             assert not all(np.isfinite(a).all() for a in gr), i
+
+
+def test_batch_full_sweep_20000_steps_sampled(torch_dev, oracle):
+    """The k(V) sweep exactly as the benchmark times it: 256 runs, one
+    persistent launch of the configured 20000 steps.  Three runs are checked
+    against the oracle (the longest, one near V = 0.1 and one at small V); the
+    oracle runs are independent and go to threads (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2303_09671_amd import pf
+    runs = I.batch_runs()
+    base = I.base_params(dim=1)
+    phi, cs, cl, offs = I.batch_fields(runs)
+    steps = 20000
+    sample = sorted({int(np.argmax([r["N"] for r in runs])), 128, 40})
+    print(f"case: full sweep 20000 steps, sampled runs {sample}", flush=True)
+    with ThreadPoolExecutor(max_workers=len(sample)) as ex:
+        futs = [ex.submit(oracle_batch, oracle, base, [runs[i]], steps) for i in sample]
+        t = [_dev(torch_dev, a) for a in (phi, cs, cl)]
+        h = pf.pf_create(base, *t, runs=runs, offsets=offs)
+        pf.pf_step(h, steps)
+        torch_dev.cuda.synchronize()
+        g = [x.cpu().numpy() for x in t]
+        refs = [f.result()[0] for f in futs]
+    for i, ref in zip(sample, refs):
+        o, N = offs[i], runs[i]["N"]
+        gr = [a[o:o + N] for a in g]
+        if all(np.isfinite(a).all() for a in ref):
+            assert_parity(gr, ref, what=f"run {i} N={N} V={runs[i]['V']:.3g}")
+        else:
+            assert not all(np.isfinite(a).all() for a in gr), i
