@@ -123,6 +123,32 @@ def bench_batch(torch, pf, steps, seq_steps=None):
                 speedup_per_step=(t_seq / seq_steps) / (t_batch / steps), cell_updates_per_s=cells * steps / t_batch)
 
 
+def bench_big(torch, pf, p3, steps=40, warmup=5):
+    """The 3D step at 1024 x 1024 x 512 cells (5.4e8 cells; 26 GB of fields and
+    twins), built on the device: kernel time per step against the same 48 B
+    per cell-update."""
+    from paper_2303_09671_amd import inputs as I
+    nx, ny, nz = 1024, 1024, 512
+    p = dict(p3, n=(nx, ny, nz), z0=(nz // 4) * p3["dx"])
+    f = I.device_front(nx, ny, nz, p["dx"], p["z0"], p["ke"], 1e-3, 11)
+    h = pf.pf_create(p, *(x.view(-1) for x in f))
+    pf.pf_step(h, warmup)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    pf.pf_step(h, steps)
+    b.record()
+    torch.cuda.synchronize()
+    k = a.elapsed_time(b) / 1e3 / steps
+    cells = nx * ny * nz
+    ach = BYTES_PER_CELL * cells / k / 1e9
+    del h, f
+    torch.cuda.empty_cache()
+    return dict(cells=cells, steps=steps, kernel_avg_us=k * 1e6, cell_updates_per_s=cells / k, achieved_GBs=ach,
+                frac=ach / HBM_PEAK_GBS)
+
+
 def bench_adjoint(torch, nsteps=10000):
     """Adjoint/forward step-time ratio on the adjoint fit workloads (64 1D runs
     N = 2048; 2D 512^2), over nsteps with checkpoints every 100 steps: forward
@@ -294,6 +320,7 @@ def main():
         extra["batch_256_runs"] = bench_batch(torch, pf, 20000, seq_steps=2000)
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
+        extra["3d_1024x1024x512"] = bench_big(torch, pf, p3)
         # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
         pe = dict(p3, model=1, eps_grad=1e-4)
         te, ke_, ce, _, _ = time_domain(torch, pf, pe, pert3, 500, 10)

@@ -64,6 +64,26 @@ def planar_front(dim: int, n, dx: float, z0: float, ke: float, W: float = 1.0,
     return phi, cs, cl
 
 
+def device_front(nx: int, ny: int, nz: int, dx: float, z0: float, ke: float, amp: float, seed: int):
+    """A perturbed 3D planar front built on the current CUDA device plane by plane
+    (no host copy of a multi-GB state): phi0(z) + amp (2 xi - 1) 4 phi0 (1 - phi0)
+    with xi from torch's seeded device generator, c_s = k_e, c_l = 1.  Returns
+    three contiguous float64 tensors of shape [nz][ny][nx]."""
+    import torch
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    z = (torch.arange(nz, dtype=torch.float64, device="cuda") + 0.5) * dx
+    prof = 1.0 / (1.0 + torch.exp(math.sqrt(2.0) * (z - z0)))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    for k in range(nz):
+        xi = torch.rand((ny, nx), generator=g, dtype=torch.float64, device="cuda")
+        p = prof[k]
+        phi[k] = p + amp * (2.0 * xi - 1.0) * 4.0 * p * (1.0 - p)
+    cs = torch.full((nz, ny, nx), ke, dtype=torch.float64, device="cuda")
+    cl = torch.ones((nz, ny, nx), dtype=torch.float64, device="cuda")
+    return phi, cs, cl
+
+
 def base_params(**kw) -> dict:
     p = dict(ALLOY)
     p.update(dict(dx=DX, V=0.1, dt=0.128, z0=0.0, dim=1, n=(1, 1, 1), periodic=(0, 0, 0)))

@@ -282,3 +282,57 @@ def test_batch_full_sweep_20000_steps_sampled(torch_dev, oracle):
             assert_parity(gr, ref, what=f"run {i} N={N} V={runs[i]['V']:.3g}")
         else:
             assert not all(np.isfinite(a).all() for a in gr), i
+
+
+def _window(a, x, y, z, w):
+    """(2w+1)^3 window of a [nz][ny][nx] array centred on (x, y, z): periodic
+    in x and y, clipped to the domain in z."""
+    nz, ny, nx = a.shape
+    zs = np.arange(max(z - w, 0), min(z + w + 1, nz))
+    xs = np.arange(x - w, x + w + 1) % nx
+    ys = np.arange(y - w, y + w + 1) % ny
+    return a[np.ix_(zs, ys, xs)], int(zs[0])
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_3d_half_billion_cells_sampled(torch_dev, oracle, model):
+    """A 1024 x 1024 x 512 grid (5.4e8 cells, 26 GB of fields and twins on
+    the device), one step in the production launch configuration.  Sampled
+    windows (periodic wrap in x and y, tile and z edges, the interface) are
+    compared with an oracle step of the same window on the cells whose
+    dependency cone (radius 2) lies inside it."""
+    from paper_2303_09671_amd import pf
+    torch = torch_dev
+    nx, ny, nz = 1024, 1024, 512
+    p, _, pert = I.config_3d()
+    p = dict(p, n=(nx, ny, nz), z0=(nz // 4) * I.DX, model=model, eps_grad=1e-4 if model else p["eps_grad"])
+    print(f"case: 3D {nx}x{ny}x{nz} one step, model={model}", flush=True)
+    phi, cs, cl = I.device_front(nx, ny, nz, p["dx"], p["z0"], p["ke"], 1e-3, 11)
+    w = 5
+    zi = nz // 4
+    centres = [(0, 0, zi), (31, 7, zi - 1), (32 * 17, 8 * 50 + 7, zi + 2), (nx - 1, ny - 1, zi), (500, 300, 3),
+               (700, 900, nz - 2), (100, 200, zi + 30)]
+    host0 = {}
+    for (x, y, z) in centres:
+        lo, hi = max(z - w, 0), min(z + w + 1, nz)
+        sl = [t[lo:hi].cpu().numpy() for t in (phi, cs, cl)]
+        host0[(x, y, z)] = [_window(a, x, y, z - lo, w)[0] for a in sl] + [lo]
+    h = pf.pf_create(p, phi.view(-1), cs.view(-1), cl.view(-1))
+    pf.pf_step(h, 1)
+    torch.cuda.synchronize()
+    assert pf.pf_check(h) == pf.PF_OK
+    for (x, y, z), (wp, ws, wl, lo) in host0.items():
+        hi = min(z + w + 1, nz)
+        g = [_window(t[lo:hi].cpu().numpy(), x, y, z - lo, w)[0] for t in (phi, cs, cl)]
+        nzw = wp.shape[0]
+        po = oracle_params(oracle, dict(p, n=(2 * w + 1, 2 * w + 1, nzw), periodic=(0, 0, 0)))
+        ref = oracle.step(po, wp.ravel(), ws.ravel(), wl.ravel(), 1, n0=0, shift=lo)
+        assert ref[3] == lo  # no window shift in the first step
+        # cells at least 3 from every cut face of the window (domain faces in z are real)
+        zlo = 0 if lo == 0 else 3
+        zhi = nzw if lo + nzw == nz else nzw - 3
+        inner = (slice(zlo, zhi), slice(3, 2 * w - 2), slice(3, 2 * w - 2))
+        for name, a, r in zip(("phi", "c_s", "c_l"), g, ref[:3]):
+            r = r.reshape(a.shape)
+            e = float(np.max(np.abs(a[inner] - r[inner])) / np.max(np.abs(r[inner])))
+            assert e <= TOL, f"window {(x, y, z)} {name}: {e:.3e}"
