@@ -126,7 +126,7 @@ def test_3d_ragged_with_shift(torch_dev, oracle, periodic):
     assert abs(E - oracle.energy(oracle_params(oracle, p), *ref[:3], n=steps, shift=ref[3])) <= 1e-10 * abs(E)
 
 
-@pytest.mark.parametrize("dim,quintic,ap", [(2, 1, -2.0), (2, 0, -1.5), (3, 0, 0.0), (3, 1, -2.0)])
+@pytest.mark.parametrize("dim,quintic,ap", [(2, 1, -2.0), (2, 0, -1.5), (2, 0, 0.0), (3, 0, 0.0), (3, 1, -2.0)])
 def test_interpolation_variants(torch_dev, oracle, dim, quintic, ap):
     """Cubic h and a nonzero a_p (Eq. interpolation2) through the 2D/3D step:
     the step kernels are compiled separately for a_p = 0 and a_p != 0."""
