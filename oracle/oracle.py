@@ -12,7 +12,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 * :func:`solute`    -- total solute, max c and its first index (Eq. model1, k_v of Sec. V.C);
 * :func:`front`     -- the phi = 1/2 front (topmost crossing per column) and its
                        temperature (interface temperature of Sec. V.C);
-* :func:`pointwise` and :func:`phi_t` -- per-cell quantities for the pins.
+* :func:`pointwise`, :func:`phi_t` and :func:`face_fluxes` -- per-cell and
+                       per-face quantities for the pins.
+
+``mutate`` (default 0) plants one known mistake in the oracle so that a test
+can show which pin catches it; only the pin tests set it.
 
 Parameters are a plain ``dict`` (see :data:`DEFAULTS`); fields are float64
 numpy arrays in the grid layout (axis 0 fastest, growth axis last).
@@ -30,9 +34,9 @@ LIB_OMP_PATH = os.path.join(_HERE, "liborc_omp.so")
 
 #: Default nondimensional parameters (lengths in W0, time in W0^2/D_l, c in c_inf).
 DEFAULTS = dict(
-    dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0, model=0,
-    dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=1.2,
-    b=1e-4, ap=0.0, inv_lT=1.0 / 444.0, V=0.1, z0=256 * 0.8, eps_grad=1e-20,
+    dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0, model=0, mutate=0,
+    dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=2.0,
+    b=1e-4, ap=0.0, inv_lT=1.0 / 444.0, V=0.1, z0=256 * 0.8, eps_grad=3e-3,
 )
 
 
@@ -40,7 +44,7 @@ class _Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
         ("quintic", C.c_int32), ("drag_variant", C.c_int32), ("model", C.c_int32),
-        ("dx", C.c_double), ("dt", C.c_double), ("W", C.c_double), ("Mphi", C.c_double),
+        ("mutate", C.c_int32), ("pad_", C.c_int32), ("dx", C.c_double), ("dt", C.c_double), ("W", C.c_double), ("Mphi", C.c_double),
         ("lambda0", C.c_double), ("Ds", C.c_double), ("ke", C.c_double), ("A", C.c_double),
         ("b", C.c_double), ("ap", C.c_double), ("inv_lT", C.c_double), ("V", C.c_double),
         ("z0", C.c_double), ("eps_grad", C.c_double),
@@ -86,6 +90,8 @@ def _load(path):
     L.orc_phi_t.restype = C.c_int
     L.orc_front.argtypes = [C.POINTER(_Params), dp, C.c_long, C.c_int64, dp]
     L.orc_front.restype = C.c_int
+    L.orc_face_fluxes.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_long, C.c_int64, C.c_int, dp, dp, dp, dp]
+    L.orc_face_fluxes.restype = C.c_int
     if L.orc_params_size() != C.sizeof(_Params):
         raise RuntimeError("oracle parameter layout mismatch")
     return L
@@ -112,6 +118,7 @@ def _cparams(p: dict) -> _Params:
     s.quintic = int(p["quintic"])
     s.drag_variant = int(p["drag_variant"])
     s.model = int(p.get("model", 0))
+    s.mutate = int(p.get("mutate", 0))
     for f in ("dx", "dt", "W", "Mphi", "lambda0", "Ds", "ke", "A", "b", "ap", "inv_lT", "V", "z0",
               "eps_grad"):
         setattr(s, f, float(p[f]))
@@ -184,6 +191,20 @@ def front(p: dict, phi, n: int = 0, shift: int = 0) -> dict:
     out = np.zeros(5)
     lib().orc_front(C.byref(_cparams(p)), _ptr(phi), int(n), int(shift), _ptr(out))
     return dict(z=out[0], zmin=out[1], zmax=out[2], T=out[3], ncol=int(out[4]))
+
+
+def face_fluxes(p: dict, phi, cs, cl, k: int, n: int = 0, shift: int = 0):
+    """Fluxes through the face between each cell and its neighbour +e_k:
+    ``(J_s, J_l, J_mix, p_face)`` (d c/dt = div J convention; zero on
+    boundary faces).  J_mix is the equal-potential model's flux (Eq.
+    solute_nonvar); J_s, J_l those of the separate-kinetics model."""
+    phi, cs, cl = _fields(phi, cs, cl, p)
+    js, jl, jm, pf = (np.zeros_like(phi) for _ in range(4))
+    rc = lib().orc_face_fluxes(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), int(n), int(shift), int(k),
+                               _ptr(js), _ptr(jl), _ptr(jm), _ptr(pf))
+    if rc != 0:
+        raise RuntimeError("orc_face_fluxes failed")
+    return js, jl, jm, pf
 
 
 def pointwise(p: dict, phi: float, cs: float, cl: float, cleq: float) -> dict:

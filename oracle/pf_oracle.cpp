@@ -94,6 +94,8 @@ struct OrcParams {
   int32_t quintic;      // 1: h = phi^3(6phi^2-15phi+10); 0: h = phi^2(3-2phi)
   int32_t drag_variant; // 0: drive from Eq. model18 (used); 1: printed reduced form (mutation tests only)
   int32_t model;        // 0: separate kinetics of c_s and c_l; 1: mu_s = mu_l imposed pointwise
+  int32_t mutate;       // 0 (used); > 0 plants one known mistake, for the pin tests only (see Mutation)
+  int32_t pad_;
   double dx, dt;
   double W;        // interface width / W0
   double Mphi;     // phi mobility in units of 1/alpha at W = W0; alpha = W / Mphi
@@ -106,6 +108,20 @@ struct OrcParams {
   double V;        // pulling speed
   double z0;       // initial interface position (lab frame)
   double eps_grad; // scale of the smooth |grad phi|^2 gate
+};
+
+// Planted mistakes, selected by OrcParams::mutate.  They exist only so that
+// the tests can show that each of their pins fails when the corresponding term
+// of the equations is wrong; the oracle proper runs with mutate = 0.
+enum Mutation : int32_t {
+  MUT_NONE = 0,
+  MUT_SWAP_AT_WEIGHTS = 1,     // anti-trapping weights M_s(1-p)/Mbar and b M_l p/Mbar exchanged
+  MUT_FLIP_AT_SIGN = 2,        // anti-trapping terms of both fluxes with the opposite sign
+  MUT_DROP_CROSS = 3,          // cross term X of the phi equation left out
+  MUT_DROP_PREFACTOR = 4,      // (1-A)^2 term of the phi prefactor left out
+  MUT_COMPACT_TRANSVERSE = 5,  // transverse face gradients from the low-side cell only
+  MUT_ISOTHERM_BACKWARDS = 6,  // frozen temperature pulled with the opposite sign of V t
+  MUT_LAB_NO_SHIFT = 7,        // lab height of a cell without the window shift count
 };
 
 // Parameters promoted to the working scalar type; theta = (A, Mphi, W) may carry tangents.
@@ -183,6 +199,7 @@ Grid make_grid(const OrcParams& P) {
 // Equilibrium liquid concentration of the frozen temperature field at the
 // lab-frame height z and time t (Eqs. dil7, ds1; reference (c_inf, T_s) at z0).
 inline double cleq_of(const OrcParams& P, double zlab, double t) {
+  if (P.mutate == MUT_ISOTHERM_BACKWARDS) t = -t;
   return (1.0 - (1.0 - P.ke) * (zlab - P.z0 - P.V * t) * P.inv_lT) / P.ke;
 }
 
@@ -270,10 +287,12 @@ T phi_t_at(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, cons
   // Prefactor: 1/M_phi + (c_s-c_l)^2 (1-A)^2 b p(1-p) / (Mbar (b p + 1 - p)) / |grad phi|^2
   T pref = w.alpha + w.lambda * q.dc * q.dc * onemA * onemA * P.b * pq /
                          (q.Mbar * (P.b * q.p + q.q)) * gam;
+  if (P.mutate == MUT_DROP_PREFACTOR) pref = w.alpha;
   // Cross term: (c_s-c_l)(1-A) p(1-p)/Mbar (M_s grad mu_s - b M_l grad mu_l) . grad phi / |grad phi|^2
   T dot = 0.0;
   for (int k = 0; k < P.dim; ++k) dot = dot + (P.Ds * gcs[k] - P.b * gcl[k]) * gphi[k];
   T cross = w.lambda * q.dc * onemA * pq / q.Mbar * dot * gam;
+  if (P.mutate == MUT_DROP_CROSS) cross = 0.0;
   T rhs = w.W2 * lap - dfdw_of(phi[i]) - w.lambda * q.dG * q.dp + cross;
   return rhs / pref;
 }
@@ -310,6 +329,8 @@ bool face_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, 
     for (int j = 0; j < P.dim; ++j) {
       if (j == k) {
         grad[f][j] = (fld[f][bidx] - fld[f][a]) / dx;
+      } else if (P.mutate == MUT_COMPACT_TRANSVERSE) {
+        grad[f][j] = cdiff(g, fld[f], c, j, dx);
       } else {
         grad[f][j] = 0.5 * (cdiff(g, fld[f], c, j, dx) + cdiff(g, fld[f], cb, j, dx));
       }
@@ -331,8 +352,11 @@ bool face_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, 
   T Mbar = Ms * qf + P.b * Ml * pf;
   T qn = Ms * Ml * (P.b * pf + qf) / Mbar;  // Eq. normal2 reduced: M_s M_l (b p + 1 - p)/Mbar
   T at = (1.0 - w.A) * dcf * grad[0][k] * gam * phitf;
-  Js = qn * n_mubar + P.Ds * t_cs + at * (Ms * qf / Mbar);
-  Jl = qn * n_mubar + t_cl - at * (P.b * Ml * pf / Mbar);
+  T ws = Ms * qf / Mbar, wl = P.b * Ml * pf / Mbar;  // anti-trapping weights of Eqs. cs_nonvar, cl_nonvar
+  if (P.mutate == MUT_SWAP_AT_WEIGHTS) std::swap(ws, wl);
+  if (P.mutate == MUT_FLIP_AT_SIGN) at = -at;
+  Js = qn * n_mubar + P.Ds * t_cs + at * ws;
+  Jl = qn * n_mubar + t_cl - at * wl;
   return true;
 }
 
@@ -387,17 +411,12 @@ bool mixture_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* ph
   return true;
 }
 
-// One forward-Euler step n -> n+1 in place.  s_shift is the number of window
-// shifts done so far (lab height of cell iz is (iz + s + 1/2) dx).
+// Pointwise quantities, mu_bar and phi_t of every cell at time t (shift count s).
 template <class T>
-void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n, int64_t* s_shift) {
-  Grid g = make_grid(P);
+void cell_stage(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, const T* cs, const T* cl,
+                double t, int64_t s, StepWork<T>& S) {
   const long N = g.ncell;
   const int gz = P.dim - 1;
-  const double t = (double)n * P.dt;
-  if (P.model == 1)  // c_s is not a state variable of this model: it follows c_l
-    for (long i = 0; i < N; ++i) cs[i] = P.ke * cl[i];
-  StepWork<T> S;
   S.phit.assign(N, T(0.0));
   S.mubar.assign(N, T(0.0));
   S.pw.resize(N);
@@ -409,7 +428,7 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
       for (int c0 = 0; c0 < g.n[0]; ++c0) {
         const int c[3] = {c0, c1, c2};
         long i = g.lin(c);
-        double zlab = ((double)c[gz] + (double)(*s_shift) + 0.5) * P.dx;
+        double zlab = ((double)c[gz] + (P.mutate == MUT_LAB_NO_SHIFT ? 0.0 : (double)s) + 0.5) * P.dx;
         S.pw[i] = pointwise(P, w, phi[i], cs[i], cl[i], cleq_of(P, zlab, t));
         S.mubar[i] = S.pw[i].mubar;
       }
@@ -421,6 +440,20 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
         long i = g.lin(c);
         S.phit[i] = phi_t_at(P, w, g, phi, cs, cl, S.pw[i], c);
       }
+}
+
+// One forward-Euler step n -> n+1 in place.  s_shift is the number of window
+// shifts done so far (lab height of cell iz is (iz + s + 1/2) dx).
+template <class T>
+void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n, int64_t* s_shift) {
+  Grid g = make_grid(P);
+  const long N = g.ncell;
+  const int gz = P.dim - 1;
+  const double t = (double)n * P.dt;
+  if (P.model == 1)  // c_s is not a state variable of this model: it follows c_l
+    for (long i = 0; i < N; ++i) cs[i] = P.ke * cl[i];
+  StepWork<T> S;
+  cell_stage(P, w, g, phi, cs, cl, t, *s_shift, S);
   std::vector<T> nphi(N), ncs(N), ncl(N);
 #pragma omp parallel for collapse(2) schedule(static)
   for (int c2 = 0; c2 < g.n[2]; ++c2)
@@ -663,6 +696,36 @@ int orc_front(const OrcParams* P, const double* phi, long n, int64_t s_shift, do
   return 0;
 }
 
+// Face fluxes for tests: for every cell c, the solid and liquid fluxes
+// (the brackets of Eqs. cs_nonvar, cl_nonvar, in the sign convention
+// d c / dt = div J + sources) and the mixture flux of Eq. solute_nonvar
+// (mixture_flux, the equal-potential model's flux) through the face between c
+// and c + e_k, and p at that face.  Boundary faces of non-periodic axes give
+// zero.  Computed from the state at step n (shift count s) with the cell-stage
+// quantities of that step.
+int orc_face_fluxes(const OrcParams* P, const double* phi, const double* cs, const double* cl, long n,
+                    int64_t s_shift, int k, double* js, double* jl, double* jmix, double* pface) {
+  if (!P || k < 0 || k >= P->dim) return -1;
+  Grid g = make_grid(*P);
+  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
+  StepWork<double> S;
+  cell_stage(*P, w, g, phi, cs, cl, (double)n * P->dt, s_shift, S);
+  int c[3];
+  for (c[2] = 0; c[2] < g.n[2]; ++c[2])
+    for (c[1] = 0; c[1] < g.n[1]; ++c[1])
+      for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
+        long i = g.lin(c);
+        double a = 0.0, b = 0.0, m = 0.0;
+        bool inner = face_flux(*P, w, g, phi, cs, cl, S, c, k, a, b);
+        mixture_flux(*P, w, g, phi, cs, cl, S, c, k, m);
+        if (js) js[i] = a;
+        if (jl) jl[i] = b;
+        if (jmix) jmix[i] = m;
+        if (pface) pface[i] = inner ? p_of(0.5 * (phi[i] + phi[g.at(c, k, +1)]), P->quintic, P->ap) : 0.0;
+      }
+  return 0;
+}
+
 // Pointwise quantities for tests: out = [h, p, p', f_dw', dmu, mubar, dG].
 int orc_pointwise(const OrcParams* P, double phi, double cs, double cl, double cleq, double* out) {
   WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
@@ -681,18 +744,10 @@ int orc_pointwise(const OrcParams* P, double phi, double cs, double cl, double c
 int orc_phi_t(const OrcParams* P, const double* phi, const double* cs, const double* cl, long n,
               int64_t s_shift, double* phit) {
   Grid g = make_grid(*P);
-  const int gz = P->dim - 1;
   WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
-  const double t = (double)n * P->dt;
-  int c[3];
-  for (c[2] = 0; c[2] < g.n[2]; ++c[2])
-    for (c[1] = 0; c[1] < g.n[1]; ++c[1])
-      for (c[0] = 0; c[0] < g.n[0]; ++c[0]) {
-        long i = g.lin(c);
-        double zlab = ((double)c[gz] + (double)s_shift + 0.5) * P->dx;
-        Pointwise<double> q = pointwise(*P, w, phi[i], cs[i], cl[i], cleq_of(*P, zlab, t));
-        phit[i] = phi_t_at(*P, w, g, phi, cs, cl, q, c);
-      }
+  StepWork<double> S;
+  cell_stage(*P, w, g, phi, cs, cl, (double)n * P->dt, s_shift, S);
+  for (long i = 0; i < g.ncell; ++i) phit[i] = S.phit[i];
   return 0;
 }
 

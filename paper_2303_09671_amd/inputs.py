@@ -29,11 +29,11 @@ ALLOY = dict(
     W=1.0,              # interface width / W0
     Mphi=1.0,           # phi mobility: alpha = tau D_l / W0^2 = W / Mphi
     lambda0=0.04462,    # Omega c_inf / H at W = W0 (I (W/d0) k_e / (1-k_e)^2 with W/d0 = 1)
-    A=1.2,              # source / trapping coefficient
+    A=2.0,              # source / trapping coefficient (the Si-As fit of Sec. V.D)
     b=1e-4, ap=0.0,     # interpolation set 2 constants: b = D_s/D_l (symmetric q_n), a_p = 0
     quintic=1,
     inv_lT=1.0 / 444.0, # 1 / thermal length l_T = dT0 / G
-    eps_grad=1e-20,     # gate on |grad phi|^2
+    eps_grad=3e-3,      # scale of the smooth gate G / (G^2 + eps^2) on 1/|grad phi|^2
 )
 
 DX = 0.8
@@ -118,14 +118,14 @@ def config_bands(N: int = 2048, steps: int = 200000):
     liquidus slope -4 K/%, c_inf = 9 %, so the freezing range is dT0 = 84 K;
     D_l = 1.5e-8 m^2/s) with W = 13.5 nm, G = 1.4e6 K/m (l_T = dT0 / G =
     6e-5 m = 4444 W), v_p = 0.3 m/s (V = v_p W / D_l = 0.27) and D_s/D_l = 1e-3;
-    b = 1e-3 and lambda0 = I k_e / (1 - k_e)^2 (W/d0 = 1), A = 1.2 (the
-    explicit scheme is stable there; A = 2 of the paper's fit is not);
+    b = 1e-3 and lambda0 = I k_e / (1 - k_e)^2 (W/d0 = 1), A = 2 (the
+    paper's Si-As fit);
     dt = 0.2 dx^2, front at N/4, no-flux ends, 200000 steps (about 1.6
     thermal times l_T / V)."""
     I0 = 1.0 / (3.0 * math.sqrt(2.0))
     ke = 0.3
     p = base_params(dim=1, n=(N, 1, 1), V=0.27, dt=0.2 * DX * DX, z0=(N // 4) * DX)
-    p.update(ke=ke, Ds=1e-3, b=1e-3, A=1.2, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=1.0 / 4444.0)
+    p.update(ke=ke, Ds=1e-3, b=1e-3, A=2.0, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=1.0 / 4444.0)
     return p, steps
 
 

@@ -111,7 +111,7 @@ def test_kks_reduction(oracle):
     N = 40
     ke, Ds = 0.3, 0.05
     P = oracle.params(dim=1, n=(N, 1, 1), model=1, A=1.0, ke=ke, Ds=Ds, b=ke * Ds, V=0.0, inv_lT=0.0,
-                      z0=16.0, dt=0.01, lambda0=0.2)
+                      z0=16.0, dt=0.01, lambda0=0.2, eps_grad=1e-20)
     z = (np.arange(N) + 0.5) * P["dx"]
     phi = 1.0 / (1.0 + np.exp(math.sqrt(2.0) * (z - 16.0) / 1.3))  # every |grad phi| well above eps
     cl = 1.0 / ke * (1.0 + 0.2 * np.sin(0.37 * np.arange(N)))

@@ -119,8 +119,7 @@ def test_openmp_build_is_bit_identical(oracle, model):
     """The all-cores timing build (OpenMP cell loops) steps exactly as the
     single-thread build: every cell is independent within a step."""
     import os
-    P = oracle.params(dim=3, n=(12, 10, 16), periodic=(1, 0, 0), V=0.6, dt=0.03, z0=5 * 0.8, model=model,
-                      eps_grad=1e-4 if model else 1e-20)
+    P = oracle.params(dim=3, n=(12, 10, 16), periodic=(1, 0, 0), V=0.6, dt=0.03, z0=5 * 0.8, model=model)
     phi, cs, cl = (a.ravel() for a in I.planar_front(3, P["n"], 0.8, P["z0"], P["ke"], amp=0.05, seed=3))
     old = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "4"

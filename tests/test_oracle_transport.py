@@ -70,28 +70,47 @@ def test_single_phase_conservation_exact(oracle):
     assert abs(t1 - t0) < 1e-12 * abs(t0)
 
 
-def test_two_phase_conservation_converges(oracle):
-    """The discrete scheme conserves c = p c_s + (1-p) c_l only up to its
-    truncation error; the drift over t = 16 shrinks under refinement
-    (dt = 0.05 dx^2), by at least 3x per halving of dx."""
+def _two_phase_drifts(oracle, **kw):
     drifts = []
     for dx in (0.8, 0.4, 0.2):
         dt = 0.05 * dx * dx
         N = int(round(160.0 / dx))
-        P = oracle.params(dim=1, n=(N, 1, 1), V=0.0, inv_lT=0.0, z0=64.0, dt=dt, dx=dx)
+        P = oracle.params(dim=1, n=(N, 1, 1), V=0.0, inv_lT=0.0, z0=64.0, dt=dt, dx=dx, **kw)
         phi, cs, cl = I.planar_front(1, (N,), dx, 64.0, P["ke"])
         t0, _, _ = oracle.solute(P, phi, cs, cl)
         phi2, cs2, cl2, _ = oracle.step(P, phi, cs, cl, int(round(16.0 / dt)))
         t1, _, _ = oracle.solute(P, phi2, cs2, cl2)
         drifts.append(abs(t1 - t0) / t0)
+    return drifts
+
+
+def test_two_phase_conservation_converges(oracle):
+    """The discrete scheme conserves c = p c_s + (1-p) c_l only up to its
+    truncation error; the drift over t = 16 shrinks under refinement
+    (dt = 0.05 dx^2), by at least 3x per halving of dx.  This holds where the
+    Stefan-like condition (Eq. model14) is exact, i.e. where the projector onto
+    grad phi is the exact one (gate scale eps -> 0)."""
+    drifts = _two_phase_drifts(oracle, A=1.2, eps_grad=1e-20)
     assert drifts[0] < 1e-3
     assert drifts[1] < drifts[0] / 3 and drifts[2] < drifts[1] / 3
+
+
+def test_gate_conservation_floor(oracle):
+    """With the gate scale of the workloads (eps = 3e-3) the normal projector is
+    gamma G = G^2 / (G^2 + eps^2) < 1 in the tails of the interface, where the
+    Stefan-like condition then holds only approximately: the drift stops
+    shrinking under refinement.  Measured floor at A = 2: 2.7e-3, 1.7e-3,
+    1.5e-3 for dx = 0.8, 0.4, 0.2 over t = 16 from a strongly undercooled start;
+    the bound below guards it."""
+    drifts = _two_phase_drifts(oracle, A=2.0, eps_grad=3e-3)
+    assert max(drifts) < 4e-3
+    assert drifts[2] > drifts[1] / 3  # not the truncation error: it does not converge away
 
 
 def _steady_front(oracle, V, N=1200, steps=20000):
     ke, dx = 0.14, 0.8
     zi = 200 * dx
-    P = oracle.params(dim=1, n=(N, 1, 1), V=V, dt=0.128, z0=zi)
+    P = oracle.params(dim=1, n=(N, 1, 1), V=V, dt=0.128, z0=zi, A=1.2, eps_grad=1e-20)
     z = (np.arange(N) + 0.5) * dx
     with np.errstate(over="ignore"):
         phi = 1.0 / (1.0 + np.exp(math.sqrt(2.0) * (z - zi)))
