@@ -130,6 +130,25 @@ int pf_energy(pf_handle* h, double* out);
  * partition coefficient of Sec. V.C is k = 1 / c_max.  Synchronous. */
 int pf_solute(pf_handle* h, double* total, double* cmax, int64_t* argmax);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of pf_solute and pf_energy for one domain (nbatch = 0), without
+ * a handle and without any allocation.  p describes the grid and model as for
+ * pf_create; phi, cs, cl are the caller's device fields in that layout,
+ * holding the state of step n (which sets t_n and the shift count of the
+ * frozen temperature in the energy).  Outputs are DEVICE scalars written
+ * asynchronously on `stream` (NULL = default stream); any of them may be NULL:
+ * total solute dx^d sum (p c_s + (1-p) c_l), c_max and its first linear index,
+ * and the free energy F / (H W0^d).  The reduction partials live in a static
+ * device array of the library (2 MiB per GPU, held until the process ends):
+ * grids of more than 2^28 cells are rejected with PF_EINVAL.  Every call on a
+ * GPU uses that GPU's one array, so calls that overlap in time on one GPU
+ * (other streams or host threads) race; calls ordered on one stream do not.
+ * Errors: PF_EINVAL for bad parameters (as pf_create), PF_EDEVICE for a HIP
+ * error. */
+int pf_solute_noalloc(const pf_params* p, const double* phi, const double* cs, const double* cl, int64_t n,
+                      void* stream, double* total, double* cmax, int64_t* argmax, double* energy);
+
 /* Solidification front and interface temperature (Sec. V.C reads the
  * interface temperature where phi = 1/2): in every growth-axis column the
  * topmost crossing -- the largest i with phi_i >= 1/2 > phi_{i+1} -- placed by

@@ -749,9 +749,10 @@ constexpr int RED_THREADS = 256;
 constexpr int RED_CHUNK = 4096;
 
 struct RedTab {
-  const int* chunk_run;        // run of chunk
+  const int* chunk_run;        // run of chunk (null: one domain, chunk k starts at cell k RED_CHUNK)
   const long long* chunk_beg;  // first cell (relative to the run) of chunk
-  const int* run_chunk0;       // first chunk of run (nrun + 1 entries)
+  const int* run_chunk0;       // first chunk of run (nrun + 1 entries; null with chunk_run)
+  int nchunk;                  // number of chunks of the one domain when the tables are null
 };
 
 struct Partial {
@@ -774,8 +775,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_chunks(Const c, RunTab r
   __shared__ double se[RED_THREADS], ss[RED_THREADS], sm[RED_THREADS];
   __shared__ long long sa[RED_THREADS];
   const int ch = blockIdx.x;
-  const int r = red.chunk_run[ch];
-  const long long beg = red.chunk_beg[ch];
+  const int r = red.chunk_run ? red.chunk_run[ch] : 0;
+  const long long beg = red.chunk_run ? red.chunk_beg[ch] : (long long)ch * RED_CHUNK;
   const long long N = batched ? (long long)rt.n[r] : c.ncell;
   const long long off = batched ? rt.off[r] : 0;
   const double V = batched ? rt.V[r] : c.V;
@@ -860,7 +861,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_runs(Const c, RedTab red
   __shared__ double se[RED_THREADS], ss[RED_THREADS], sm[RED_THREADS];
   __shared__ long long sa[RED_THREADS];
   const int r = blockIdx.x;
-  const int c0 = red.run_chunk0[r], c1 = red.run_chunk0[r + 1];
+  const int c0 = red.run_chunk0 ? red.run_chunk0[r] : 0;
+  const int c1 = red.run_chunk0 ? red.run_chunk0[r + 1] : red.nchunk;
   double e = 0.0, s = 0.0, mx = -INFINITY;
   long long am = -1;
   for (int k = c0 + threadIdx.x; k < c1; k += RED_THREADS) {
@@ -892,6 +894,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_runs(Const c, RedTab red
     out[r].solute = ss[0] * vol;
     out[r].cmax = sm[0];
     out[r].arg = sa[0];
+  }
+}
+
+// Copy one reduced Partial into separate device outputs (any may be null).
+__global__ void k_partial_emit(const Partial* __restrict__ in, double* energy, double* total, double* cmax,
+                               long long* argmax) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (energy) *energy = in->energy;
+    if (total) *total = in->solute;
+    if (cmax) *cmax = in->cmax;
+    if (argmax) *argmax = in->arg;
   }
 }
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -98,6 +99,7 @@ struct pf_handle {
     t.chunk_run = d_chunk_run;
     t.chunk_beg = d_chunk_beg;
     t.run_chunk0 = d_run_chunk0;
+    t.nchunk = nchunk;
     return t;
   }
 };
@@ -276,6 +278,35 @@ int fill(pf_handle* h, double* a, double v, long long n) {
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(pfk::k_fill, dim3((unsigned)blocks), dim3(256), 0, h->stream, a, v, n);
   PF_HIP(hipGetLastError());
+  return PF_OK;
+}
+
+// Reduction partials of pf_solute_noalloc: one Partial per chunk of RED_CHUNK
+// cells plus the reduced result, in a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  Host code uses
+// only the address hipGetSymbolAddress returns for the current device, never
+// the array's name.
+constexpr long long NOALLOC_MAX_CHUNKS = 65536;  // up to 2^28 cells (2 MiB)
+__device__ __align__(256) pfk::Partial scratch[NOALLOC_MAX_CHUNKS + 1];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[NOALLOC_MAX_DEVICES];
+
+// Address of the current device's scratch array, looked up once per device.
+int scratch_ptr(pfk::Partial** out) {
+  int dev = 0;
+  PF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(PF_EDEVICE, "device index beyond the scratch table");
+  ScratchSlot& s = g_scratch[dev];
+  std::call_once(s.once, [&s] { s.err = hipGetSymbolAddress(&s.ptr, HIP_SYMBOL(scratch)); });
+  if (s.err != hipSuccess || !s.ptr)
+    return fail(PF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(s.err));
+  *out = (pfk::Partial*)s.ptr;
   return PF_OK;
 }
 
@@ -549,6 +580,40 @@ int pf_solute(pf_handle* h, double* total, double* cmax, int64_t* argmax) {
     if (cmax) cmax[i] = r[i].cmax;
     if (argmax) argmax[i] = r[i].arg;
   }
+  return PF_OK;
+}
+
+int pf_solute_noalloc(const pf_params* p, const double* phi, const double* cs, const double* cl, int64_t n,
+                      void* stream, double* total, double* cmax, int64_t* argmax, double* energy) {
+  if (!p || !phi || !cs || !cl) return fail(PF_EINVAL, "null argument");
+  if (n < 0) return fail(PF_EINVAL, "n must be >= 0");
+  int rc = validate(*p);
+  if (rc) return rc;
+  if (p->nbatch != 0) return fail(PF_EINVAL, "pf_solute_noalloc takes one domain (nbatch = 0)");
+  const pfk::Const c = make_const(*p);
+  const long long nchunk = (c.ncell + pfk::RED_CHUNK - 1) / pfk::RED_CHUNK;
+  if (nchunk > NOALLOC_MAX_CHUNKS) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%lld cells exceed the scratch of pf_solute_noalloc (at most %lld)", c.ncell,
+             NOALLOC_MAX_CHUNKS * (long long)pfk::RED_CHUNK);
+    return fail(PF_EINVAL, buf);
+  }
+  pfk::Partial* part = nullptr;
+  if ((rc = scratch_ptr(&part))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  pfk::RunTab rt{};  // one domain: the run table is not read
+  pfk::RedTab red{};
+  red.nchunk = (int)nchunk;
+  // every chunk slot is written before it is read, so nothing needs clearing
+  hipLaunchKernelGGL(pfk::k_reduce_chunks, dim3((unsigned)nchunk), dim3(pfk::RED_THREADS), 0, s, c, rt, red, phi,
+                     cs, cl, (long long)n, 0, part);
+  PF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pfk::k_reduce_runs, dim3(1), dim3(pfk::RED_THREADS), 0, s, c, red, part,
+                     part + NOALLOC_MAX_CHUNKS);
+  PF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pfk::k_partial_emit, dim3(1), dim3(64), 0, s, part + NOALLOC_MAX_CHUNKS, energy, total, cmax,
+                     (long long*)argmax);
+  PF_HIP(hipGetLastError());
   return PF_OK;
 }
 

@@ -21,7 +21,7 @@ PF_OK, PF_EINVAL, PF_EUNSTABLE_DT, PF_ENONFINITE, PF_ENEGCONC, PF_EDEVICE, PF_EN
 #: C symbols the header declares (checked by the CPU test of the library).
 EXPORTS = ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy", "pf_solute",
            "pf_front", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed", "pf_destroy", "pf_strerror",
-           "pf_last_error_detail")
+           "pf_last_error_detail", "pf_solute_noalloc")
 
 
 class PFError(RuntimeError):
@@ -63,6 +63,7 @@ def lib() -> C.CDLL:
         L.pf_energy.argtypes = [vp, dp]
         L.pf_solute.argtypes = [vp, dp, dp, C.POINTER(i64)]
         L.pf_front.argtypes = [vp, dp, dp, dp, dp, C.POINTER(i64)]
+        L.pf_solute_noalloc.argtypes = [C.POINTER(pf_params), vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.pf_check.argtypes = [vp]
         L.pf_adjoint_step.argtypes = [vp, i64, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
         L.pf_adjoint_segment.argtypes = [vp, i64, i64, vp, vp, vp, i64, C.POINTER(vp), C.POINTER(vp), vp]
@@ -74,7 +75,8 @@ def lib() -> C.CDLL:
         L.pf_last_error_detail.argtypes = []
         L.pf_last_error_detail.restype = C.c_char_p
         for name in ("pf_create", "pf_step", "pf_step_traj", "pf_get_step", "pf_set_step", "pf_energy",
-                     "pf_solute", "pf_front", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed"):
+                     "pf_solute", "pf_front", "pf_check", "pf_adjoint_step", "pf_adjoint_segment", "pf_kv_seed",
+                     "pf_solute_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -191,6 +193,23 @@ def pf_solute(h: Handle):
     _check(lib().pf_solute(h.ptr, tot.ctypes.data_as(C.POINTER(C.c_double)), cm.ctypes.data_as(C.POINTER(C.c_double)),
                            am.ctypes.data_as(C.POINTER(C.c_int64))), "pf_solute")
     return tot, cm, am
+
+
+def pf_solute_noalloc(params: dict, phi, cs, cl, n: int, out, stream=None):
+    """Handle-free, allocation-free diagnostics of one domain: writes
+    (total, c_max, argmax, energy) into the device tensors ``out`` =
+    (float64[1], float64[1], int64[1], float64[1]) asynchronously on the stream."""
+    import torch
+    s, _ = _make_params(params)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    for t, dt in zip(out, (torch.float64, torch.float64, torch.int64, torch.float64)):
+        if not (t.is_cuda and t.dtype == dt and t.numel() >= 1):
+            raise TypeError("outputs must be device tensors (float64, float64, int64, float64)")
+    _check(lib().pf_solute_noalloc(C.byref(s), C.c_void_p(_dev_ptr(phi)), C.c_void_p(_dev_ptr(cs)),
+                                   C.c_void_p(_dev_ptr(cl)), int(n), C.c_void_p(stream.cuda_stream),
+                                   C.c_void_p(out[0].data_ptr()), C.c_void_p(out[1].data_ptr()),
+                                   C.c_void_p(out[2].data_ptr()), C.c_void_p(out[3].data_ptr())), "pf_solute_noalloc")
 
 
 def pf_front(h: Handle) -> dict:
