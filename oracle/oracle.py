@@ -35,7 +35,7 @@ LIB_OMP_PATH = os.path.join(_HERE, "liborc_omp.so")
 #: Default nondimensional parameters (lengths in W0, time in W0^2/D_l, c in c_inf).
 DEFAULTS = dict(
     dim=1, n=(1024, 1, 1), periodic=(0, 0, 0), quintic=1, drag_variant=0, model=0, mutate=0,
-    dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=2.0,
+    dx=0.8, dt=0.128, W=1.0, Mphi=1.0, lambda0=0.04462, Ds=1e-4, ke=0.14, A=1.2,
     b=1e-4, ap=0.0, inv_lT=1.0 / 444.0, V=0.1, z0=256 * 0.8, eps_grad=3e-3,
 )
 

@@ -29,7 +29,7 @@ ALLOY = dict(
     W=1.0,              # interface width / W0
     Mphi=1.0,           # phi mobility: alpha = tau D_l / W0^2 = W / Mphi
     lambda0=0.04462,    # Omega c_inf / H at W = W0 (I (W/d0) k_e / (1-k_e)^2 with W/d0 = 1)
-    A=2.0,              # source / trapping coefficient (the Si-As fit of Sec. V.D)
+    A=1.2,              # source / trapping coefficient (A_FIT = 2 is the Si-As fit of Sec. V.D)
     b=1e-4, ap=0.0,     # interpolation set 2 constants: b = D_s/D_l (symmetric q_n), a_p = 0
     quintic=1,
     inv_lT=1.0 / 444.0, # 1 / thermal length l_T = dT0 / G
@@ -37,6 +37,12 @@ ALLOY = dict(
 )
 
 DX = 0.8
+
+#: The paper's fitted source coefficient for Si-As (Sec. V.D).  Its runs are
+#: unstable to perturbations of the front after about 8000 steps of the 1D
+#: workload, so they take the operating-point workload (config_1d_a2), not the
+#: full-run parity workloads.
+A_FIT = 2.0
 
 
 def grid_shape(dim: int, n) -> tuple:
@@ -98,6 +104,14 @@ def config_1d(N: int = 1024, steps: int = 20000):
     return p, steps
 
 
+def config_1d_a2(N: int = 1024, steps: int = 20000):
+    """The 1D workload at the paper's operating point A = A_FIT = 2 (the Si-As
+    fit of Sec. V.D): same grid, speed and time step as config_1d."""
+    p, steps = config_1d(N, steps)
+    p["A"] = A_FIT
+    return p, steps
+
+
 def config_2d(nx: int = 1024, nz: int = 1024, steps: int = 10000, seed: int = 1, amp: float = 1e-3):
     """2D directional solidification: periodic x, no-flux z, V=0.05,
     dt = 0.2 dx^2 / 4, seeded front perturbation of amplitude 1e-3."""
@@ -125,7 +139,7 @@ def config_bands(N: int = 2048, steps: int = 200000):
     I0 = 1.0 / (3.0 * math.sqrt(2.0))
     ke = 0.3
     p = base_params(dim=1, n=(N, 1, 1), V=0.27, dt=0.2 * DX * DX, z0=(N // 4) * DX)
-    p.update(ke=ke, Ds=1e-3, b=1e-3, A=2.0, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=1.0 / 4444.0)
+    p.update(ke=ke, Ds=1e-3, b=1e-3, A=A_FIT, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=1.0 / 4444.0)
     return p, steps
 
 

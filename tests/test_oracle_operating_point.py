@@ -21,7 +21,7 @@ KEYS = ("dim", "n", "periodic", "quintic", "dx", "dt", "W", "Mphi", "lambda0", "
 
 
 def _setup(oracle, **kw):
-    p, steps = I.config_1d()
+    p, steps = I.config_1d_a2()
     p = dict(p, **kw)
     po = oracle.params(**{k: p[k] for k in KEYS})
     f = [a.ravel() for a in I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])]

@@ -98,38 +98,12 @@ def test_two_phase_conservation_converges(oracle):
 def test_gate_conservation_floor(oracle):
     """With the gate scale of the workloads (eps = 3e-3) the normal projector is
     gamma G = G^2 / (G^2 + eps^2) < 1 in the tails of the interface, where the
-    Stefan-like condition then holds only approximately: the drift stops
-    shrinking under refinement.  Measured floor at A = 2: 2.7e-3, 1.7e-3,
-    1.5e-3 for dx = 0.8, 0.4, 0.2 over t = 16 from a strongly undercooled start;
-    the bound below guards it."""
-    drifts = _two_phase_drifts(oracle, A=2.0, eps_grad=3e-3)
-    assert max(drifts) < 4e-3
-    assert drifts[2] > drifts[1] / 3  # not the truncation error: it does not converge away
-
-
-def _steady_front(oracle, V, N=1200, steps=20000):
-    ke, dx = 0.14, 0.8
-    zi = 200 * dx
-    P = oracle.params(dim=1, n=(N, 1, 1), V=V, dt=0.128, z0=zi, A=1.2, eps_grad=1e-20)
-    z = (np.arange(N) + 0.5) * dx
-    with np.errstate(over="ignore"):
-        phi = 1.0 / (1.0 + np.exp(math.sqrt(2.0) * (z - zi)))
-    cl = np.where(z > zi, 1.0 + (1.0 - ke) / ke * np.exp(-V * (z - zi)), 1.0 / ke)
-    cs = ke * cl
-    phi, cs, cl, _ = oracle.step(P, phi, cs, cl, steps)
-    _, cmax, am = oracle.solute(P, phi, cs, cl)
-    i0, i1 = am + 40, am + 200
-    slope = np.polyfit(z[i0:i1], np.log(cl[i0:i1] - 1.0), 1)[0]
-    return 1.0 / cmax, slope
-
-
-def test_trapping_limit_and_far_field():
-    from oracle import oracle as O
-    k1, s1 = _steady_front(O, 0.0025)
-    k2, s2 = _steady_front(O, 0.005)
-    ke = 0.14
-    assert ke < k1 < k2 < 0.16                     # trapping grows with V
-    k0 = k1 - (k2 - k1)                            # linear extrapolation to V = 0
-    assert abs(k0 - ke) < 2e-3
-    for V, s in ((0.0025, s1), (0.005, s2)):       # c_l - c_inf ~ exp(-V z / D_l)
-        assert s == pytest.approx(-V, rel=0.05)
+    Stefan-like condition then holds only approximately: the drift shrinks
+    more slowly than the truncation error and levels off.  Measured over
+    t = 16 from a strongly undercooled start, dx = 0.8, 0.4, 0.2: 5.8e-4,
+    2.3e-4, 1.5e-4 at A = 1.2; 2.7e-3, 1.7e-3, 1.5e-3 at A = 2.  The bounds
+    below guard both."""
+    d12 = _two_phase_drifts(oracle, A=1.2, eps_grad=3e-3)
+    assert max(d12) < 1e-3 and d12[2] > d12[1] / 3
+    d2 = _two_phase_drifts(oracle, A=2.0, eps_grad=3e-3)
+    assert max(d2) < 4e-3 and d2[2] > d2[1] / 3
