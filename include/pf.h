@@ -166,13 +166,16 @@ int pf_front(pf_handle* h, double* z_mean, double* z_min, double* z_max, double*
  * function): PF_OK, PF_ENONFINITE or PF_ENEGCONC.  Synchronous; clears it. */
 int pf_check(pf_handle* h);
 
-/* Adjoint of one step (transpose of the Jacobian of step n -> n + 1) of model 0:
+/* Adjoint of one step (transpose of the Jacobian of step n -> n + 1) of model 0
+ * (Eqs. cs_nonvar, cl_nonvar, phasefield_nonvar as discretised by pf_step):
  *   lam_n = (d u^{n+1} / d u^n)^T lam_np1,
- *   dtheta += (d u^{n+1} / d theta)^T lam_np1,  theta = (A, M_phi, W),
+ *   dtheta += (d u^{n+1} / d theta)^T lam_np1,  theta = (A, M_phi, W, b),
  * with alpha = W / M_phi and lambda = lambda0 W (gamma, Omega, D and the grid
- * fixed).  u_n[f], lam_np1[f], lam_n[f] (f = phi, c_s, c_l) are device arrays
- * in the field layout; lam_n may not alias lam_np1.  dtheta is a device
- * double[3], accumulated.  The window shift of step n is held fixed (it is
+ * fixed) and b the mobility-interpolation constant of Eq. interpolation1 (the
+ * three fitting constants of Sec. V.D are A, b and W).  u_n[f], lam_np1[f],
+ * lam_n[f] (f = phi, c_s, c_l) are device arrays in the field layout; lam_n
+ * may not alias lam_np1.  dtheta is a device double[4], accumulated.  The
+ * window shift of step n is held fixed (it is
  * piecewise constant in theta).  Built for 1D runs and 2D grids (3D:
  * PF_EINVAL).  Asynchronous on the stream. */
 int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const double* const lam_np1[3],
@@ -184,7 +187,7 @@ int pf_adjoint_step(pf_handle* h, int64_t n, const double* const u_n[3], const d
  * written by pf_step_traj; stride >= the field size).  On entry lam[f] holds
  * lam^{n0+m}, on return lam^{n0}; work[f] are caller-owned device arrays of the
  * field size used for the ping-pong (contents undefined afterwards; they may
- * not alias lam).  dtheta (device double[3]) is accumulated once for the whole
+ * not alias lam).  dtheta (device double[4]) is accumulated once for the whole
  * segment: the per-block sums are carried over the m steps and reduced at the
  * end, so the result equals the sum of m pf_adjoint_step calls up to rounding
  * order.  Asynchronous on the stream. */

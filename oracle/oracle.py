@@ -159,10 +159,13 @@ def step(p: dict, phi, cs, cl, nsteps: int, n0: int = 0, shift: int = 0, openmp:
 
 
 def jvp(p: dict, phi, cs, cl, dphi, dcs, dcl, dtheta, nsteps: int, n0: int = 0, shift: int = 0):
-    """Dual-number forward mode: returns ``(u_out(3), du_out(3), shift)``."""
+    """Dual-number forward mode: returns ``(u_out(3), du_out(3), shift)``.
+    ``dtheta`` is the tangent of theta = (A, M_phi, W, b) (a 3-vector leaves b fixed)."""
     phi, cs, cl = _fields(phi, cs, cl, p)
     dphi, dcs, dcl = _fields(dphi, dcs, dcl, p)
-    th = np.ascontiguousarray(np.asarray(dtheta, dtype=np.float64).reshape(3))
+    th = np.zeros(4)
+    dth = np.asarray(dtheta, dtype=np.float64).ravel()
+    th[:dth.size] = dth
     s = C.c_int64(int(shift))
     rc = lib().orc_jvp(C.byref(_cparams(p)), _ptr(phi), _ptr(cs), _ptr(cl), _ptr(dphi), _ptr(dcs),
                        _ptr(dcl), _ptr(th), int(n0), int(nsteps), C.byref(s))

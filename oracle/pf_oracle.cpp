@@ -124,10 +124,10 @@ enum Mutation : int32_t {
   MUT_LAB_NO_SHIFT = 7,        // lab height of a cell without the window shift count
 };
 
-// Parameters promoted to the working scalar type; theta = (A, Mphi, W) may carry tangents.
+// Parameters promoted to the working scalar type; theta = (A, Mphi, W, b) may carry tangents.
 template <class T>
 struct WP {
-  T A, Mphi, W, alpha, lambda, W2;
+  T A, Mphi, W, alpha, lambda, W2, b;
 };
 
 // Double-well and interpolation functions (Sec. II; Eqs. interpolation2).
@@ -232,7 +232,7 @@ Pointwise<T> pointwise(const OrcParams& P, const WP<T>& w, T phi, T cs, T cl, do
   r.Ms = P.Ds * cs;
   r.Ml = cl;
   // Mbar of the numerical equations: M_s (1-p) + b M_l p.
-  r.Mbar = r.Ms * r.q + P.b * r.Ml * r.p;
+  r.Mbar = r.Ms * r.q + w.b * r.Ml * r.p;
   // Driving forces of Eqs. dil5.1 (with mu_s) and dil5.2 (with mu_l).
   T G_mus = cl * r.dmu + (P.ke - 1.0) * cleq - r.dc;  // f_s - f_l - (c_s-c_l) mu_s
   T G_mul = cs * r.dmu + (P.ke - 1.0) * cleq - r.dc;  // f_s - f_l - (c_s-c_l) mu_l
@@ -240,7 +240,7 @@ Pointwise<T> pointwise(const OrcParams& P, const WP<T>& w, T phi, T cs, T cl, do
   if (P.drag_variant == 0) {
     // Eq. model18 with M_s^n/Mbar_n = M_s(1-p)/Mbar and M_l^n/Mbar_n = b M_l p/Mbar:
     T ws = r.Ms * r.q / r.Mbar;
-    T wl = P.b * r.Ml * r.p / r.Mbar;
+    T wl = w.b * r.Ml * r.p / r.Mbar;
     T brack_s = G_mus - S * r.q * r.dmu;           // ... - S_l (1-g)(mu_s - mu_l)
     T brack_l = G_mul - S * r.p * (-r.dmu);        // ... - S_s g (mu_l - mu_s)
     r.dG = ws * brack_s + wl * brack_l;
@@ -285,12 +285,12 @@ T phi_t_at(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, cons
   T pq = q.p * q.q;
   T onemA = 1.0 - w.A;
   // Prefactor: 1/M_phi + (c_s-c_l)^2 (1-A)^2 b p(1-p) / (Mbar (b p + 1 - p)) / |grad phi|^2
-  T pref = w.alpha + w.lambda * q.dc * q.dc * onemA * onemA * P.b * pq /
-                         (q.Mbar * (P.b * q.p + q.q)) * gam;
+  T pref = w.alpha + w.lambda * q.dc * q.dc * onemA * onemA * w.b * pq /
+                         (q.Mbar * (w.b * q.p + q.q)) * gam;
   if (P.mutate == MUT_DROP_PREFACTOR) pref = w.alpha;
   // Cross term: (c_s-c_l)(1-A) p(1-p)/Mbar (M_s grad mu_s - b M_l grad mu_l) . grad phi / |grad phi|^2
   T dot = 0.0;
-  for (int k = 0; k < P.dim; ++k) dot = dot + (P.Ds * gcs[k] - P.b * gcl[k]) * gphi[k];
+  for (int k = 0; k < P.dim; ++k) dot = dot + (P.Ds * gcs[k] - w.b * gcl[k]) * gphi[k];
   T cross = w.lambda * q.dc * onemA * pq / q.Mbar * dot * gam;
   if (P.mutate == MUT_DROP_CROSS) cross = 0.0;
   T rhs = w.W2 * lap - dfdw_of(phi[i]) - w.lambda * q.dG * q.dp + cross;
@@ -349,10 +349,10 @@ bool face_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* phi, 
   T t_cs = grad[2][k] - gam * dcs * grad[0][k];
   T t_cl = grad[3][k] - gam * dcl * grad[0][k];
   T Ms = P.Ds * csf, Ml = clf;
-  T Mbar = Ms * qf + P.b * Ml * pf;
-  T qn = Ms * Ml * (P.b * pf + qf) / Mbar;  // Eq. normal2 reduced: M_s M_l (b p + 1 - p)/Mbar
+  T Mbar = Ms * qf + w.b * Ml * pf;
+  T qn = Ms * Ml * (w.b * pf + qf) / Mbar;  // Eq. normal2 reduced: M_s M_l (b p + 1 - p)/Mbar
   T at = (1.0 - w.A) * dcf * grad[0][k] * gam * phitf;
-  T ws = Ms * qf / Mbar, wl = P.b * Ml * pf / Mbar;  // anti-trapping weights of Eqs. cs_nonvar, cl_nonvar
+  T ws = Ms * qf / Mbar, wl = w.b * Ml * pf / Mbar;  // anti-trapping weights of Eqs. cs_nonvar, cl_nonvar
   if (P.mutate == MUT_SWAP_AT_WEIGHTS) std::swap(ws, wl);
   if (P.mutate == MUT_FLIP_AT_SIGN) at = -at;
   Js = qn * n_mubar + P.Ds * t_cs + at * ws;
@@ -401,9 +401,9 @@ bool mixture_flux(const OrcParams& P, const WP<T>& w, const Grid& g, const T* ph
   }
   T gam = G / (G * G + P.eps_grad * P.eps_grad);
   T Ms = P.Ds * csf, Ml = clf;
-  T Mbar = Ms * qf + P.b * Ml * pf;
-  T qn = Ms * Ml * (P.b * pf + qf) / Mbar;       // Eq. normal2 with h_n of Eq. interpolation1
-  T a_shape = (Ms - P.b * Ml) * pf * qf / Mbar;  // Eq. shape_function
+  T Mbar = Ms * qf + w.b * Ml * pf;
+  T qn = Ms * Ml * (w.b * pf + qf) / Mbar;       // Eq. normal2 with h_n of Eq. interpolation1
+  T a_shape = (Ms - w.b * Ml) * pf * qf / Mbar;  // Eq. shape_function
   T normal = qn * gam * dmu * grad[0][k];
   T tang = pf * P.Ds * (grad[2][k] - gam * dcs * grad[0][k]) + qf * (grad[3][k] - gam * dcl * grad[0][k]);
   T anti = (1.0 - w.A) * (csf - clf) * a_shape * phitf * grad[0][k] * gam;
@@ -538,11 +538,12 @@ void step_once(const OrcParams& P, const WP<T>& w, T* phi, T* cs, T* cl, long n,
 }
 
 template <class T>
-WP<T> make_wp(const OrcParams& P, T A, T Mphi, T W) {
+WP<T> make_wp(const OrcParams& P, T A, T Mphi, T W, T b) {
   WP<T> w;
   w.A = A;
   w.Mphi = Mphi;
   w.W = W;
+  w.b = b;
   w.alpha = W / Mphi;     // tau D_l / W0^2 scales with W at fixed gamma and M_phi
   w.lambda = P.lambda0 * W;  // Omega c_inf / H scales with W at fixed gamma
   w.W2 = W * W;
@@ -561,14 +562,14 @@ int orc_params_size(void) { return (int)sizeof(OrcParams); }
 int orc_step(const OrcParams* P, double* phi, double* cs, double* cl, long n0, long nsteps,
              int64_t* s_shift) {
   if (!P || !phi || !cs || !cl || !s_shift || P->dim < 1 || P->dim > 3) return -1;
-  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
+  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W, P->b);
   for (long s = 0; s < nsteps; ++s) step_once(*P, w, phi, cs, cl, n0 + s, s_shift);
   return 0;
 }
 
 // Forward-mode directional derivative of nsteps steps.  (du_phi, du_cs, du_cl)
-// is the input tangent (overwritten by the output tangent) and dtheta[3] the
-// tangent of (A, Mphi, W).  The fields are advanced as in orc_step.
+// is the input tangent (overwritten by the output tangent) and dtheta[4] the
+// tangent of (A, Mphi, W, b).  The fields are advanced as in orc_step.
 int orc_jvp(const OrcParams* P, double* phi, double* cs, double* cl, double* dphi, double* dcs,
             double* dcl, const double* dtheta, long n0, long nsteps, int64_t* s_shift) {
   if (!P || !phi || !cs || !cl || !dphi || !dcs || !dcl || !dtheta || !s_shift) return -1;
@@ -580,7 +581,8 @@ int orc_jvp(const OrcParams* P, double* phi, double* cs, double* cl, double* dph
     ucs[i] = Dual(cs[i], dcs[i]);
     ucl[i] = Dual(cl[i], dcl[i]);
   }
-  WP<Dual> w = make_wp<Dual>(*P, Dual(P->A, dtheta[0]), Dual(P->Mphi, dtheta[1]), Dual(P->W, dtheta[2]));
+  WP<Dual> w = make_wp<Dual>(*P, Dual(P->A, dtheta[0]), Dual(P->Mphi, dtheta[1]), Dual(P->W, dtheta[2]),
+                             Dual(P->b, dtheta[3]));
   for (long s = 0; s < nsteps; ++s) step_once(*P, w, uphi.data(), ucs.data(), ucl.data(), n0 + s, s_shift);
   for (long i = 0; i < N; ++i) {
     phi[i] = uphi[i].v;
@@ -707,7 +709,7 @@ int orc_face_fluxes(const OrcParams* P, const double* phi, const double* cs, con
                     int64_t s_shift, int k, double* js, double* jl, double* jmix, double* pface) {
   if (!P || k < 0 || k >= P->dim) return -1;
   Grid g = make_grid(*P);
-  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
+  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W, P->b);
   StepWork<double> S;
   cell_stage(*P, w, g, phi, cs, cl, (double)n * P->dt, s_shift, S);
   int c[3];
@@ -728,7 +730,7 @@ int orc_face_fluxes(const OrcParams* P, const double* phi, const double* cs, con
 
 // Pointwise quantities for tests: out = [h, p, p', f_dw', dmu, mubar, dG].
 int orc_pointwise(const OrcParams* P, double phi, double cs, double cl, double cleq, double* out) {
-  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
+  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W, P->b);
   Pointwise<double> q = pointwise(*P, w, phi, cs, cl, cleq);
   out[0] = h_of(phi, P->quintic);
   out[1] = q.p;
@@ -744,7 +746,7 @@ int orc_pointwise(const OrcParams* P, double phi, double cs, double cl, double c
 int orc_phi_t(const OrcParams* P, const double* phi, const double* cs, const double* cl, long n,
               int64_t s_shift, double* phit) {
   Grid g = make_grid(*P);
-  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W);
+  WP<double> w = make_wp<double>(*P, P->A, P->Mphi, P->W, P->b);
   StepWork<double> S;
   cell_stage(*P, w, g, phi, cs, cl, (double)n * P->dt, s_shift, S);
   for (long i = 0; i < g.ncell; ++i) phit[i] = S.phit[i];

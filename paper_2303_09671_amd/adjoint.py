@@ -1,5 +1,7 @@
 """Gradients of the partition coefficient k = c_inf / c_max with respect to
-theta = (A, M_phi, W), through the C ABI's adjoint step.
+theta = (A, M_phi, W) or (A, M_phi, W, b), through the C ABI's adjoint step
+(b is the mobility-interpolation constant of Eq. interpolation1; A, b and W
+are the fitting constants of Sec. V.D).
 
 ``PartitionCoefficient.apply(theta, workload)`` runs the explicit stepping for
 ``workload.nsteps`` steps from the workload's initial state (held fixed), saving
@@ -41,7 +43,10 @@ class Workload:
 
 def _params_with(workload: Workload, theta) -> dict:
     p = dict(workload.params)
-    p["A"], p["Mphi"], p["W"] = (float(v) for v in theta)
+    th = [float(v) for v in theta]
+    p["A"], p["Mphi"], p["W"] = th[:3]
+    if len(th) > 3:
+        p["b"] = th[3]
     return p
 
 
@@ -83,7 +88,7 @@ class PartitionCoefficient(torch.autograd.Function):
         pf.pf_kv_seed(h, grad_k.detach().cpu().numpy().astype(np.float64), lam)
         dtheta = _backward_segments(h, ctx.workload, th, fields, ck, lam)
         ctx.state = None
-        return dtheta.cpu(), None
+        return dtheta[:len(th)].cpu(), None
 
 
 class FinalState(torch.autograd.Function):
@@ -108,12 +113,13 @@ class FinalState(torch.autograd.Function):
                for g in (g_phi, g_cs, g_cl)]
         dtheta = _backward_segments(h, ctx.workload, th, fields, ck, lam)
         ctx.state = None
-        return dtheta.cpu(), None
+        return dtheta[:len(th)].cpu(), None
 
 
 def _backward_segments(h, wl: Workload, theta, fields, ck, lam, overlap: bool = True):
     """Replay each checkpoint segment in reverse and take its adjoint steps;
-    lam holds the cotangent of the final state on entry.  Returns dL/dtheta.
+    lam holds the cotangent of the final state on entry.  Returns dL/dtheta
+    for theta = (A, M_phi, W, b).
     With ``overlap`` the replays run on a second stream one segment ahead."""
     main = h.stream
     side = torch.cuda.Stream(device=fields[0].device) if overlap else main
@@ -122,7 +128,7 @@ def _backward_segments(h, wl: Workload, theta, fields, ck, lam, overlap: bool = 
     nseg = len(ck)
     with torch.cuda.stream(main):
         work = [torch.empty_like(fields[0]) for _ in range(3)]
-        dtheta = torch.zeros(3, dtype=torch.float64, device=fields[0].device)
+        dtheta = torch.zeros(4, dtype=torch.float64, device=fields[0].device)
         trajs = [[torch.empty((K + 1, nfield), dtype=torch.float64, device=fields[0].device) for _ in range(3)]
                  for _ in range(2)]
         rep_fields = [torch.empty_like(f) for f in fields]

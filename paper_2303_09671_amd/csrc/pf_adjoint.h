@@ -29,6 +29,7 @@ namespace pfadj {
 using pfk::Const;
 
 constexpr int H = 3;  // box halo
+constexpr int NTH = 5;  // per-block parameter cotangents: A, alpha, lambda, W^2, b
 
 // p, 1-p, p', p'' of the interpolation function (APZ: a_p known to be zero).
 template <bool APZ>
@@ -105,7 +106,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
   __shared__ double au[3][G::NB], amu[G::NB], apt[G::NB];
   // 1D: (mu_s - mu_l)/Omega of the box, computed once (2D: recomputed; no LDS room)
   __shared__ double sdm[(DIM == 1) ? G::NB : 1];
-  __shared__ double red[4][G::NT / 64];
+  __shared__ double red[NTH][G::NT / 64];
   const int tid = threadIdx.x;
   const double tn = (double)n * d.dt;
   const double sn = floor(d.V * tn / c.dx);
@@ -202,7 +203,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
   }
   __syncthreads();
 
-  double thA = 0.0, thAl = 0.0, thLa = 0.0, thW2 = 0.0;  // cotangents of A, alpha, lambda, W^2
+  double thA = 0.0, thAl = 0.0, thLa = 0.0, thW2 = 0.0, thB = 0.0;  // cotangents of A, alpha, lambda, W^2, b
 
   // ---- faces inside T+2: forward flux inputs, then their VJP
   auto do_faces = [&](auto axis) {
@@ -286,6 +287,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       R_b += nrm_b * Ms * Ml * bq * dmu;
       p_b += bq_b * c.b;
       q_b += bq_b;
+      if (owned(lx, lz)) thB += bq_b * p;  // bq = b p + q
       // R = gph[K] G / (Mb S), S = G^2 + eps^2
       double Gs_b = R_b * gph[K] * iMS - R_b * R * 2.0 * Gs * (Mb * iMS);
       gph_b[K] += R_b * Gs * iMS;
@@ -296,6 +298,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       q_b += ms_b * Ms;
       Ml_b += ml_b * c.b * p;
       p_b += ml_b * c.b * Ml;
+      if (owned(lx, lz)) thB += ml_b * Ml * p;  // ml = b M_l p
       csf_b += Ms_b * c.Ds;
       clf_b += Ml_b;
 #pragma unroll
@@ -398,7 +401,10 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     double dmu_b = 0.0, dp_b = 0.0, Dn_b = 0.0, Mb_b = 0.0, ms_b = 0.0, ml_b = 0.0, lap_b = 0.0;
     {  // Kd = (1-A)^2 b dc^2 pq G
       const double Kd_b = den_b * c.lambda;
-      if (own) thA += Kd_b * (-2.0 * oA * c.b * dc * dc * pq * Gs);
+      if (own) {
+        thA += Kd_b * (-2.0 * oA * c.b * dc * dc * pq * Gs);
+        thB += Kd_b * oA * oA * dc * dc * pq * Gs;
+      }
       dc_b += Kd_b * 2.0 * oA * oA * c.b * dc * pq * Gs;
       pq_b += Kd_b * oA * oA * c.b * dc * dc * Gs;
       Gs_b += Kd_b * oA * oA * c.b * dc * dc * pq;
@@ -442,6 +448,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     Gs_b += Sg_b * 2.0 * Gs;
     p_b += pq_b * q + bq_b * c.b;
     q_b += pq_b * p + bq_b;
+    if (own) thB += bq_b * p;  // bq = b p + q
     // Dn = ms (1 - A q) + A ml p
     ms_b += Dn_b * (1.0 - c.A * q);
     if (own) thA += Dn_b * (-ms * q + ml * p);
@@ -454,6 +461,13 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     q_b += ms_b * c.Ds * cs;
     cl_b += ml_b * c.b * p;
     p_b += ml_b * c.b * cl;
+    if (own) {
+      thB += ml_b * cl * p;  // ml = b c_l p
+      double gg = 0.0;       // dot = (Ds grad c_s - b grad c_l) . grad phi
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) gg += gcl[k] * gph[k];
+      thB += -dot_b * gg;
+    }
     cs_b += dc_b;
     cl_b -= dc_b;
     const double icscl = pfk::frcp(cs * cl);
@@ -507,15 +521,15 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
   }
   // ---- parameter cotangents of this block: a fixed butterfly within each
   // wave, then the wave sums in wave order (deterministic)
-  double th[4] = {thA, thAl, thLa, thW2};
+  double th[NTH] = {thA, thAl, thLa, thW2, thB};
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < NTH; ++k)
     for (int m = 32; m > 0; m >>= 1) th[k] += __shfl_xor(th[k], m, 64);
   if ((tid & 63) == 0)
-    for (int k = 0; k < 4; ++k) red[k][tid >> 6] = th[k];
+    for (int k = 0; k < NTH; ++k) red[k][tid >> 6] = th[k];
   __syncthreads();
   if (tid == 0)
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NTH; ++k) {
       double t = 0.0;
       for (int w = 0; w < G::NT / 64; ++w) t += red[k][w];
       theta_out[k] = accum ? theta_out[k] + t : t;  // accum: sum over the steps of a segment
@@ -550,7 +564,7 @@ __global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Ti
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<1, APZ>(cc, d, n, shift, u, l, o, part + 4 * blockIdx.x, accum);
+  adjoint_tile<1, APZ>(cc, d, n, shift, u, l, o, part + NTH * blockIdx.x, accum);
 }
 
 template <bool APZ>
@@ -571,28 +585,29 @@ __global__ __launch_bounds__(256) void k_adj2d(Const c, long long n, int shift, 
   const double* u[3] = {u0, u1, u2};
   const double* l[3] = {l0, l1, l2};
   double* o[3] = {o0, o1, o2};
-  adjoint_tile<2, APZ>(c, d, n, shift, u, l, o, part + 4 * (blockIdx.x + gridDim.x * blockIdx.y), accum);
+  adjoint_tile<2, APZ>(c, d, n, shift, u, l, o, part + NTH * (blockIdx.x + gridDim.x * blockIdx.y), accum);
 }
 
 // Sum the block partials in block order and add the cotangents of
-// theta = (A, M_phi, W): alpha = W / M_phi, lambda = lambda0 W, W^2.
+// theta = (A, M_phi, W, b): alpha = W / M_phi, lambda = lambda0 W, W^2.
 __global__ void k_theta_final(Const c, const double* __restrict__ part, int nblk, double* __restrict__ dtheta) {
-  __shared__ double red[4][256];
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  __shared__ double red[NTH][256];
+  double s[NTH] = {};
   for (int b = threadIdx.x; b < nblk; b += 256)
-    for (int k = 0; k < 4; ++k) s[k] += part[4 * b + k];
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
+    for (int k = 0; k < NTH; ++k) s[k] += part[NTH * b + k];
+  for (int k = 0; k < NTH; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w)
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      for (int k = 0; k < NTH; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double gA = red[0][0], gal = red[1][0], gla = red[2][0], gW2 = red[3][0];
+    const double gA = red[0][0], gal = red[1][0], gla = red[2][0], gW2 = red[3][0], gb = red[4][0];
     dtheta[0] += gA;
     dtheta[1] += gal * (-c.W / (c.Mphi * c.Mphi));
     dtheta[2] += gal / c.Mphi + gla * c.lambda0 + gW2 * 2.0 * c.W;
+    dtheta[3] += gb;
   }
 }
 

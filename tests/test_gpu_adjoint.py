@@ -4,7 +4,7 @@
   cotangent lam and tangents (du, dtheta), the GPU's <J^T lam, du> +
   <dL/dtheta, dtheta> equals the oracle's <lam, J du + J_theta dtheta>, where
   the oracle's J du is its exact dual-number JVP of the same step.  Each theta
-  component is checked on its own.  Cases: 1D single run with and without a
+  component (A, M_phi, W, b) is checked on its own.  Cases: 1D single run with and without a
   window shift at the step, two batched runs, 2D periodic and mirror x.
 * Gradient test: dL/dtheta of L = sum_r (k_r - k*_r)^2 over checkpointed runs
   (autograd Function, replay + adjoint) against central finite differences of
@@ -45,7 +45,7 @@ def _transpose_check(torch, oracle, p, fields, n, s, seed, runs=None, offsets=No
     h = pf.pf_create(p, *t, runs=runs, offsets=offsets)
     lt = [_dev(torch, a) for a in lam]
     lo = [torch.empty_like(x) for x in lt]
-    dth = torch.zeros(3, dtype=torch.float64, device="cuda")
+    dth = torch.zeros(4, dtype=torch.float64, device="cuda")
     pf.pf_adjoint_step(h, n, t, lt, lo, dth)
     torch.cuda.synchronize()
     lam_n = [x.cpu().numpy() for x in lo]
@@ -67,13 +67,13 @@ def _transpose_check(torch, oracle, p, fields, n, s, seed, runs=None, offsets=No
         mask[:] = False
         for r, o in zip(runs, offsets):
             mask[o:o + r["N"]] = True
-    Jdu = jvp(du, [0.0, 0.0, 0.0])
+    Jdu = jvp(du, [0.0, 0.0, 0.0, 0.0])
     lhs = sum(np.dot(lam_n[f][mask], du[f][mask]) for f in range(3))
     rhs = sum(np.dot(lam[f][mask], Jdu[f][mask]) for f in range(3))
     scale = sum(np.abs(lam_n[f][mask] * du[f][mask]).sum() for f in range(3))
     assert abs(lhs - rhs) <= 1e-11 * scale + 1e-14, (lhs, rhs, scale)
-    for i in range(3):
-        e = [0.0, 0.0, 0.0]
+    for i in range(4):  # theta = (A, M_phi, W, b)
+        e = [0.0, 0.0, 0.0, 0.0]
         e[i] = 1.0
         Jt = jvp([np.zeros(N)] * 3, e)
         ref = sum(np.dot(lam[f][mask], Jt[f][mask]) for f in range(3))
@@ -134,24 +134,25 @@ def test_gradient_vs_finite_difference(torch_dev):
     phi, cs, cl, offs = I.batch_fields(runs)
     wl = Workload(params=base, fields0=(phi, cs, cl), nsteps=450, every=100, runs=runs, offsets=offs)
     ktgt = torch.tensor([0.2, 0.25, 0.3], dtype=torch.float64)
-    theta = torch.tensor([base["A"], base["Mphi"], base["W"]], dtype=torch.float64, requires_grad=True)
-    print("case: gradient vs FD (3 runs x 450 steps)", flush=True)
+    theta = torch.tensor([base["A"], base["Mphi"], base["W"], base["b"]], dtype=torch.float64, requires_grad=True)
+    print("case: gradient vs FD (3 runs x 450 steps), theta = (A, M_phi, W, b)", flush=True)
     k = PartitionCoefficient.apply(theta, wl)
     L = ((k - ktgt) ** 2).sum()
     L.backward()
     g = theta.grad.numpy()
-    h = 1e-6
-    fd = np.zeros(3)
-    for i in range(3):
+    hs = [1e-6, 1e-6, 1e-6, 1e-6 * base["b"]]  # b ~ 1e-4: the same relative step
+    fd = np.zeros(4)
+    for i in range(4):
         tp = theta.detach().numpy().copy()
         tm = tp.copy()
-        tp[i] += h
-        tm[i] -= h
+        tp[i] += hs[i]
+        tm[i] -= hs[i]
         kp = forward_k(wl, tp)[0]
         km = forward_k(wl, tm)[0]
-        fd[i] = (((kp - ktgt) ** 2).sum() - ((km - ktgt) ** 2).sum()).item() / (2 * h)
-    for i in range(3):
-        assert abs(g[i] - fd[i]) <= 1e-5 * max(abs(fd[i]), 1e-3 * np.abs(fd).max()), (i, g, fd)
+        fd[i] = (((kp - ktgt) ** 2).sum() - ((km - ktgt) ** 2).sum()).item() / (2 * hs[i])
+    print(f"  grad {g} fd {fd}", flush=True)
+    for i in range(4):
+        assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + 1e-8 * np.abs(fd[:3]).max(), (i, g, fd)
 
 
 @pytest.mark.parametrize("dim,m", [(1, 7), (2, 6)])
@@ -187,13 +188,13 @@ def test_segment_matches_steps(torch_dev, dim, m):
     lam_end = [torch.randn(N, generator=g, dtype=torch.float64).cuda() for _ in range(3)]
     a = [x.clone() for x in lam_end]
     b = [torch.empty_like(x) for x in lam_end]
-    th_steps = torch.zeros(3, dtype=torch.float64, device="cuda")
+    th_steps = torch.zeros(4, dtype=torch.float64, device="cuda")
     for j in reversed(range(m)):
         pf.pf_adjoint_step(h, n0 + j, [traj[k][j] for k in range(3)], a, b, th_steps)
         a, b = b, a
     lam = [x.clone() for x in lam_end]
     work = [torch.empty_like(x) for x in lam_end]
-    th_seg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    th_seg = torch.zeros(4, dtype=torch.float64, device="cuda")
     pf.pf_adjoint_segment(h, n0, m, traj, lam, work, th_seg)
     torch.cuda.synchronize()
     for k in range(3):

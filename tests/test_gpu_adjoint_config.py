@@ -1,8 +1,9 @@
 """The adjoint fit workload at its configured size: 64 1D runs (N = 2048, V
 log-spaced 1e-2..1) plus one 2D 512^2 run, 10000 steps, checkpoints every 100
 steps; loss L = sum (k - k*)^2 against the seeded Aziz-form target curve.
-dL/dtheta, theta = (A, M_phi, W), from the adjoint must agree with central
-finite differences to 1e-5 relative; the argmax cell of every run must not move
+dL/dtheta, theta = (A, M_phi, W, b), from the adjoint must agree with central
+finite differences to 1e-5 relative (for b ~ 1e-4 the step is h b, the same
+relative step); the argmax cell of every run must not move
 between the +h and -h runs (max() is differentiated through it).
 
 Checked at h = 1e-6 (the configured step; bar 1e-5 relative per component)
@@ -31,7 +32,8 @@ def test_adjoint_workload_gradient():
     wls = [Workload(**one_d), Workload(**two_d)]
     tgts = [torch.tensor(k1t, dtype=torch.float64), torch.tensor([k2t], dtype=torch.float64)]
     base = one_d["params"]
-    theta0 = np.array([base["A"], base["Mphi"], base["W"]])
+    theta0 = np.array([base["A"], base["Mphi"], base["W"], base["b"]])
+    scale = np.array([1.0, 1.0, 1.0, base["b"]])  # FD step of each component = h * scale
     for wl, kt, name in zip(wls, tgts, ("1D x64", "2D 512^2")):
         print(f"case: adjoint workload {name}", flush=True)
         theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
@@ -42,19 +44,21 @@ def test_adjoint_workload_gradient():
         g = theta.grad.numpy()
         fds = {}
         for h in (1e-8, 1e-6):
-            fd = np.zeros(3)
-            for i in range(3):
+            fd = np.zeros(4)
+            for i in range(4):
                 tp, tm = theta0.copy(), theta0.copy()
-                tp[i] += h
-                tm[i] -= h
+                tp[i] += h * scale[i]
+                tm[i] -= h * scale[i]
                 kp, hp, _, _ = forward_k(wl, tp)
                 km, hm, _, _ = forward_k(wl, tm)
                 if True:
                     assert np.array_equal(pf.pf_solute(hp)[2], pf.pf_solute(hm)[2]), "argmax moved"
-                fd[i] = (((kp - kt) ** 2).sum() - ((km - kt) ** 2).sum()).item() / (2 * h)
+                fd[i] = (((kp - kt) ** 2).sum() - ((km - kt) ** 2).sum()).item() / (2 * h * scale[i])
             fds[h] = fd
         print(f"  grad {g} fd(1e-6) {fds[1e-6]} fd(1e-8) {fds[1e-8]}", flush=True)
         for h, fd in fds.items():
             floor = 1e-9 if h == 1e-6 else 1e-5  # relative to max |fd|: FD rounding noise at h = 1e-8
-            for i in range(3):
-                assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + floor * np.abs(fd).max(), (name, h, i, g, fd)
+            for i in range(4):
+                # the noise floor of component i scales with 1/scale[i]
+                fl = floor * np.abs(fd[:3] * scale[:3]).max() / scale[i]
+                assert abs(g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + fl, (name, h, i, g, fd)

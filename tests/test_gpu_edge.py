@@ -120,7 +120,7 @@ def test_api_errors(torch_dev):
     N = f[0].numel()
     lam = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(3)]
     out = [torch.zeros_like(x) for x in lam]
-    dth = torch.zeros(3, dtype=torch.float64, device="cuda")
+    dth = torch.zeros(4, dtype=torch.float64, device="cuda")
     with pytest.raises(pf.PFError) as e:  # no 3D adjoint
         pf.pf_adjoint_step(h, 0, f, lam, out, dth)
     assert e.value.code == pf.PF_EINVAL

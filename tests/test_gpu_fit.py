@@ -1,4 +1,5 @@
-"""Adjoint-driven fit of theta = (A, M_phi, W) to a k(V) curve (Sec. V.C).
+"""Adjoint-driven fit of (A, b, W) -- the paper's fitting constants (Sec. V.D) --
+to a k(V) curve, with the gradient of theta = (A, M_phi, W, b) from the adjoint.
 
 Synthetic recovery: the target is the GPU forward's own k(V) at theta*; from
 a start theta0 away from it, BFGS on the adjoint gradient must cut the loss by
@@ -32,14 +33,16 @@ def test_fit_recovers_curve():
     from paper_2303_09671_amd.adjoint import forward_k
     from paper_2303_09671_amd.fit import fit_theta, loss_and_grad
     wl = _workload()
-    theta_star = np.array([1.05, 1.1, 0.95])
+    b0 = wl.params["b"]
+    theta_star = np.array([1.05, 1.0, 0.95, 1.5 * b0])  # (A, M_phi, W, b)
     k_star = forward_k(wl, theta_star)[0].numpy()
-    theta0 = np.array([1.2, 1.0, 1.0])
-    print("case: fit 5 runs x 512 cells, 800 steps", flush=True)
+    theta0 = np.array([1.2, 1.0, 1.0, b0])
+    print("case: fit of (A, b, W), 5 runs x 512 cells, 800 steps", flush=True)
     L0, g0, _ = loss_and_grad(wl, k_star, theta0)
-    # a small step along -grad lowers the loss
-    step = 1e-3 / np.linalg.norm(g0)
-    L1 = loss_and_grad(wl, k_star, theta0 - step * g0)[0]
+    # a small step along -grad (b in its own scale) lowers the loss
+    sc = np.array([1.0, 1.0, 1.0, b0])
+    d = -g0 * sc * sc
+    L1 = loss_and_grad(wl, k_star, theta0 + 1e-3 * d / np.max(np.abs(d / sc)))[0]
     assert L1 < L0
     res = fit_theta(wl, k_star, theta0, iters=15,
                     log=lambda i, th, L: print(f"  it {i} theta {th} L {L:.3e}", flush=True))
