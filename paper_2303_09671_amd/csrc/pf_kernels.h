@@ -64,8 +64,11 @@ struct StreamGeom {
   __device__ static __forceinline__ int i1(int lx, int ly) { return (lx + 1) + BX1 * (ly + OY1); }
 };
 
+#ifndef PF_S3_MINBLOCKS
+#define PF_S3_MINBLOCKS 3
+#endif
 template <int DIM, int TX, int TY, bool APZ, bool EQ>
-__global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
+__global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? PF_S3_MINBLOCKS : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
                                                     double* __restrict__ oph, double* __restrict__ ocs,
@@ -153,17 +156,26 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
     cs_off[r] = gx + nx * gy;
   }
+  // Global addressing: a plane's base pointer is uniform across the
+  // workgroup; the in-plane byte offset fits 32 bits (planes hold fewer than
+  // 2^28 cells), so the loads take a scalar base and a 32-bit vector offset.
+  auto at = [](const double* base, unsigned cell) -> double {
+    return *(const double*)((const char*)base + cell * 8u);
+  };
   auto load_plane = [&](int gz) {
     const int slot = slot3(gz);
     const long long zo = plane * mirror_idx(gz, nz);
+    const double* bph = iph + zo;
+    const double* bcs = ics + zo;
+    const double* bcl = icl + zo;
 #pragma unroll
     for (int r = 0; r < NLD; ++r) {
       const int i = tid + r * G::NT;
       if (i < G::P2) {
-        const long long idx = ld_off[r] + zo;
-        su[slot][0][i] = iph[idx];
-        if constexpr (!EQ) su[slot][1][i] = ics[idx];
-        su[slot][2][i] = icl[idx];
+        const unsigned o = (unsigned)ld_off[r];
+        su[slot][0][i] = at(bph, o);
+        if constexpr (!EQ) su[slot][1][i] = at(bcs, o);
+        su[slot][2][i] = at(bcl, o);
       }
     }
   };
@@ -194,16 +206,16 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
         upS = CS(sp, ic);
         upL = su[sp][2][ic];
       } else {
-        const long long o = cs_off[r] + zup;
-        upP = iph[o];
-        upL = icl[o];
-        upS = EQ ? c.ke * upL : ics[o];
+        const unsigned o = (unsigned)cs_off[r];
+        upP = at(iph + zup, o);
+        upL = at(icl + zup, o);
+        upS = EQ ? c.ke * upL : at(ics + zup, o);
       }
       if (dn_global) {
-        const long long o = cs_off[r] + zdn;
-        dnP = iph[o];
-        dnL = icl[o];
-        dnS = EQ ? c.ke * dnL : ics[o];
+        const unsigned o = (unsigned)cs_off[r];
+        dnP = at(iph + zdn, o);
+        dnL = at(icl + zdn, o);
+        dnS = EQ ? c.ke * dnL : at(ics + zdn, o);
       } else {
         dnP = su[sm][0][ic];
         dnS = CS(sm, ic);
@@ -437,24 +449,22 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
         ncl = cl + c.dt * (divl * c.inv_dx2 + src);
       }
       errbits |= check_bits(nph, ncs, ncl);
-      const long long col = (long long)gxo + (long long)nx * gyo;
+      const unsigned col = (unsigned)(gxo + nx * gyo) * 8u;  // byte offset in the plane
+      auto put = [col](double* base, double v) { *(double*)((char*)base + col) = v; };
       if (!do_shift) {
-        const long long o = col + plane * z;
-        oph[o] = nph;
-        ocs[o] = ncs;
-        ocl[o] = ncl;
+        put(oph + plane * z, nph);
+        put(ocs + plane * z, ncs);
+        put(ocl + plane * z, ncl);
       } else {
         if (z >= 1) {
-          const long long o = col + plane * (z - 1);
-          oph[o] = nph;
-          ocs[o] = ncs;
-          ocl[o] = ncl;
+          put(oph + plane * (z - 1), nph);
+          put(ocs + plane * (z - 1), ncs);
+          put(ocl + plane * (z - 1), ncl);
         }
         if (z == nz - 1) {
-          const long long o = col + plane * z;
-          oph[o] = 0.0;
-          ocs[o] = c.ke;
-          ocl[o] = 1.0;
+          put(oph + plane * z, 0.0);
+          put(ocs + plane * z, c.ke);
+          put(ocl + plane * z, 1.0);
         }
       }
     }

@@ -160,7 +160,7 @@ int validate(const pf_params& p) {
     if (p.n[p.dim - 1] < 3) return fail(PF_EINVAL, "the growth axis needs at least 3 cells");
     long long tr = 1;  // cells of one transverse plane: indexed with 32-bit offsets
     for (int k = 0; k + 1 < p.dim; ++k) tr *= p.n[k];
-    if (tr >= (1LL << 31) - 64) return fail(PF_EINVAL, "a transverse plane must hold fewer than 2^31 cells");
+    if (tr > (1LL << 28)) return fail(PF_EINVAL, "a transverse plane must hold at most 2^28 cells");
   }
   if (!(p.dx > 0) || !(p.dt > 0) || !(p.W > 0) || !(p.Mphi > 0) || !(p.lambda0 > 0) || !(p.Ds > 0) ||
       !(p.b > 0))
@@ -696,7 +696,7 @@ static int adj_prepare(pf_handle* h, int* nblk_out) {
   if (nblk > h->ntheta_part) {
     if (h->d_theta_part) (void)hipFree(h->d_theta_part);
     h->d_theta_part = nullptr;
-    int rc = dalloc(&h->d_theta_part, (size_t)nblk * 4);
+    int rc = dalloc(&h->d_theta_part, (size_t)nblk * pfadj::NTH);
     if (rc) return rc;
     h->ntheta_part = nblk;
   }
