@@ -88,27 +88,41 @@ def time_domain(torch, pf, p, pert, steps, warmup, diag_every=100):
     return total, kern, cells, h, t
 
 
-def bench_batch(torch, pf, steps, seq_steps=None):
-    """256-run k(V) sweep: one persistent launch of `steps` steps vs 256
-    sequential single-run launches of `seq_steps` steps each (default: the same;
-    fewer keeps the sequential leg short, and the speed-up is taken per step)."""
-    seq_steps = steps if seq_steps is None else seq_steps
+def bench_batch(torch, pf, steps, seq_steps=2000, tail=1000):
+    """256-run k(V) sweep: one persistent launch of `steps` steps (timed) vs
+    256 sequential single-run launches from the same fresh initial states,
+    `seq_steps` steps each (timed; their per-step cost is extrapolated to
+    `steps`).  Per run, after the persistent launch: k = 1/c_max, the front and
+    its velocity over `tail` further (untimed) steps (post-processing of two
+    pf_front readings); a run is steady when that velocity is within 2 % of its
+    pulling speed, and lost when no phi = 1/2 crossing is left in its window."""
     from paper_2303_09671_amd import inputs as I
     runs = I.batch_runs()
     base = I.base_params(dim=1)
     phi, cs, cl, offs = I.batch_fields(runs)
     t = [dev(torch, a) for a in (phi, cs, cl)]
     h = pf.pf_create(base, *t, runs=runs, offsets=offs)
-    pf.pf_step(h, 10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pf.pf_step(h, steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    # sequential: one handle per run, launched one after the other
+    _, cm, _ = pf.pf_solute(h)
+    k = 1.0 / cm
+    f0 = pf.pf_front(h)
+    pf.pf_step(h, tail)
+    f1 = pf.pf_front(h)
+    V = np.array([r["V"] for r in runs])
+    dt = np.array([r["dt"] for r in runs])
+    v = (f1["z"] - f0["z"]) / (tail * dt)
+    finite = np.isfinite(k)
+    lost = (f0["ncol"] == 0) | (f1["ncol"] == 0)
+    steady = finite & ~lost & (np.abs(v / V - 1.0) < 0.02)
+    # sequential: one handle per run on a fresh copy of the initial state
+    ts = [dev(torch, a) for a in (phi, cs, cl)]
     hs = []
     for r, o in zip(runs, offs):
-        tt = [x[o:o + r["N"]] for x in t]
+        tt = [x[o:o + r["N"]] for x in ts]
         pr = dict(base, dim=1, n=(r["N"], 1, 1), V=r["V"], dt=r["dt"], z0=r["z0"])
         hs.append(pf.pf_create(pr, *tt))
     torch.cuda.synchronize()
@@ -118,9 +132,17 @@ def bench_batch(torch, pf, steps, seq_steps=None):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     cells = sum(r["N"] for r in runs)
+    per_run = [dict(V=float(a), N=r["N"], k=(float(b) if np.isfinite(b) else None),
+                    status=("lost" if l else "steady" if s_ else "transient" if f_ else "non-finite"))
+               for a, r, b, l, s_, f_ in zip(V, runs, k, lost, steady, finite)]
     return dict(runs=len(runs), steps_each=steps, cells_total=cells, persistent_s=t_batch,
                 sequential_steps_each=seq_steps, sequential_s=t_seq,
-                speedup_per_step=(t_seq / seq_steps) / (t_batch / steps), cell_updates_per_s=cells * steps / t_batch)
+                sequential_extrapolated_s=t_seq * steps / seq_steps,
+                speedup_per_step=(t_seq / seq_steps) / (t_batch / steps), cell_updates_per_s=cells * steps / t_batch,
+                finite_k=int(finite.sum()), steady=int(steady.sum()), lost=int(lost.sum()),
+                transient=int((finite & ~lost & ~steady).sum()),
+                steady_V_range=([float(V[steady].min()), float(V[steady].max())] if steady.any() else None),
+                per_run=per_run)
 
 
 def bench_big(torch, pf, p3, steps=40, warmup=5):
@@ -317,12 +339,12 @@ def main():
         d1 = time.perf_counter() - t0
         _, cm, _ = pf.pf_solute(h1)
         extra["1d_1024_20000_steps"] = dict(seconds=d1, cell_updates_per_s=1024 * steps1 / d1, k=float(1.0 / cm[0]))
-        extra["batch_256_runs"] = bench_batch(torch, pf, 20000, seq_steps=2000)
+        extra["batch_256_runs"] = bench_batch(torch, pf, 20000)
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
         extra["3d_1024x1024x512"] = bench_big(torch, pf, p3)
         # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
-        pe = dict(p3, model=1, eps_grad=1e-4)
+        pe = dict(p3, model=1)
         te, ke_, ce, _, _ = time_domain(torch, pf, pe, pert3, 500, 10)
         # its state is (phi, c_l): 16 B read and 24 B written per cell-update
         ae = BYTES_PER_CELL_EQ * ce / (ke_ / 500) / 1e9
@@ -330,7 +352,7 @@ def main():
                                                cell_updates_per_s=ce * 500 / te, algorithmic_bytes_per_cell=BYTES_PER_CELL_EQ,
                                                achieved_GBs=ae, frac=ae / HBM_PEAK_GBS)
         t1e = [dev(torch, a) for a in f1]
-        h1e = pf.pf_create(dict(p1, model=1, eps_grad=1e-4), *t1e)
+        h1e = pf.pf_create(dict(p1, model=1), *t1e)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pf.pf_step(h1e, steps1)

@@ -94,16 +94,31 @@ typedef struct pf_params {
 typedef struct pf_handle pf_handle;
 
 /* Create a handle over caller-owned device fields phi, cs, cl (see layout
- * above) and the HIP stream `stream` (NULL = default stream).  Validates the
- * parameters: PF_EINVAL for a bad grid or model constants (0 < k_e < 1, D_s,
- * W, M_phi, lambda0, dx, dt > 0, b > 0, b p + 1 - p > 0 and q_n >= 0 over
- * phi in [0, 1]); PF_EUNSTABLE_DT if dt exceeds
+ * above) and the HIP stream `stream` (NULL = default stream) for the problem
+ * of Secs. II-III: the set-2 equations of motion (Eqs. cs_nonvar, cl_nonvar,
+ * phasefield_nonvar) of a dilute alloy (Eq. dil1) in the frozen temperature
+ * field of Eq. ds1, discretised as in Sec. V.A.  Validates the parameters:
+ * PF_EINVAL for a bad grid or model constants (0 < k_e < 1, D_s, W, M_phi,
+ * lambda0, dx, dt > 0, b > 0, b p + 1 - p > 0 and q_n >= 0 over phi in [0, 1],
+ * transverse planes of at most 2^28 cells); PF_EUNSTABLE_DT if dt exceeds
  * 0.9 min(dx^2/(2 d max(1, D_s)), alpha dx^2/(2 d W^2), 0.2 dx/V) per run.
- * The step counter starts at 0.  On success *out receives the handle. */
+ * The step counter starts at 0.  On success *out receives the handle.
+ *
+ * Regime (measured, not checked here): the bound above covers diffusion, phi
+ * relaxation and window advection only.  Where the phase field flattens inside
+ * an interface, the (1-A)^2 term of the phi prefactor and the anti-trapping
+ * flux grow as 1/|grad phi|^2 and phi_t/|grad phi|; with |1 - A| of order one
+ * (the paper's A = 2) and a gate scale eps_grad well below 1e-3 this diverges
+ * from an undercooled start within tens of steps at any dt (the error word
+ * then reports PF_ENEGCONC or PF_ENONFINITE).  eps_grad = 3e-3 steps A = 2 on
+ * the 1D, 2D, 3D, k(V) and band workloads; slow steady fronts (V ~ 0.005) at
+ * A = 2 can still fail after ~1e4 steps through a ghost-concentration
+ * oscillation. */
 int pf_create(const pf_params* p, double* phi, double* cs, double* cl, void* stream, pf_handle** out);
 
-/* Advance the fields by nsteps explicit steps (asynchronous on the stream
- * unless check_every > 0).  After the stream is synchronised the caller's
+/* Advance the fields by nsteps explicit forward-Euler steps of the staggered
+ * scheme (Sec. V.A), with the moving-window shift of Sec. V.A (asynchronous on
+ * the stream unless check_every > 0).  After the stream is synchronised the caller's
  * buffers hold the state at step n + nsteps.  1D single runs and batches run
  * as one persistent launch per call; 2D/3D as one fused launch per step. */
 int pf_step(pf_handle* h, int64_t nsteps);

@@ -12,8 +12,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 namespace pfk {
 
 // Derived constants of a handle, passed by value to every kernel.
@@ -178,28 +176,16 @@ __device__ __forceinline__ double cell_rate(const Const& c, double kcl, double p
 }
 
 // EQ: the equal-potential model (mu_s = mu_l = ln c_l imposed): dmu = 0.
-// aux (optional) receives what the update of the same cell needs besides
-// phi_t: the source coefficient -A (c_s - c_l) p' (separate kinetics), or p
-// and 1 - p (equal-potential model, for the mixture concentration).
-struct NoAux {};
-template <bool APZ, bool EQ = false, class Aux = NoAux>
+template <bool APZ, bool EQ = false>
 __device__ __forceinline__ void cell_core(const Const& c, double kcl, double phi, double cs, double cl, double G,
                                           double dot, double Wlap, double eps2x, double onemAx, double& phit,
-                                          double& mubar, Aux* aux = nullptr) {
+                                          double& mubar) {
   double p, q, dp;
   interp<APZ>(c, phi, p, q, dp);
   const double ll = flog(cl);
   const double dmu = EQ ? 0.0 : flog(cs) - ll - c.log_ke;  // (mu_s - mu_l) / Omega
   mubar = ll + p * dmu;
   phit = cell_rate(c, kcl, phi, cs, cl, dmu, p, q, dp, G, dot, Wlap, eps2x, onemAx);
-  if constexpr (!std::is_same<Aux, NoAux>::value) {
-    if constexpr (EQ) {
-      aux[0] = p;
-      aux[1] = q;
-    } else {
-      aux[0] = -c.A * (cs - cl) * dp;
-    }
-  }
 }
 
 // g*[k] are the central differences (u_{+k} - u_{-k}) / (2 dx), lap the
@@ -219,17 +205,17 @@ __device__ __forceinline__ void cell_stage(const Const& c, double kcl, double ph
 
 // The same from plain differences: d*[k] = u_{+k} - u_{-k} and lsum the sum over
 // axes of u_{+k} - 2 u + u_{-k} (k = 1 / (4 dx^2)).
-template <int DIM, bool APZ = false, bool EQ = false, class Aux = NoAux>
+template <int DIM, bool APZ = false, bool EQ = false>
 __device__ __forceinline__ void cell_stage_raw(const Const& c, double kcl, double phi, double cs, double cl,
                                                const double* dph, const double* dcs, const double* dcl,
-                                               double lsum, double& phit, double& mubar, Aux* aux = nullptr) {
+                                               double lsum, double& phit, double& mubar) {
   double G = 0.0, dot = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     G += dph[k] * dph[k];
     dot += (c.Ds * dcs[k] - c.b * dcl[k]) * dph[k];
   }
-  cell_core<APZ, EQ, Aux>(c, kcl, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar, aux);
+  cell_core<APZ, EQ>(c, kcl, phi, cs, cl, G, dot, c.W2_dx2 * lsum, c.eps2r, c.onemA_4dx2, phit, mubar);
 }
 
 // Face stage: solid and liquid fluxes (brackets of Eqs. cs_nonvar, cl_nonvar)

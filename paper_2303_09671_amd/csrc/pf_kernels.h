@@ -64,11 +64,8 @@ struct StreamGeom {
   __device__ static __forceinline__ int i1(int lx, int ly) { return (lx + 1) + BX1 * (ly + OY1); }
 };
 
-#ifndef PF_S3_MINBLOCKS
-#define PF_S3_MINBLOCKS 3
-#endif
 template <int DIM, int TX, int TY, bool APZ, bool EQ>
-__global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? PF_S3_MINBLOCKS : 1) void k_stream(Const c, const double* __restrict__ iph,
+__global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) void k_stream(Const c, const double* __restrict__ iph,
                                                     const double* __restrict__ ics,
                                                     const double* __restrict__ icl,
                                                     double* __restrict__ oph, double* __restrict__ ocs,

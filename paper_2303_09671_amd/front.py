@@ -2,9 +2,10 @@
 
 The interface temperature and velocity of Sec. V.C / Figs. 8-9 are read from
 the phi = 1/2 front: every ``every`` steps the library reports the front
-height z (lab frame) and (T_I - T_s)/dT0; the interface velocity is the
-centred difference of z in time.  All arithmetic on the fields runs in the HIP
-library; this module only records the scalars.
+height z (lab frame) and (T_I - T_s)/dT0.  All arithmetic on the fields runs
+in the HIP library; this module records those scalars and post-processes the
+series: the interface velocity is the centred difference of the recorded
+heights in time (a derived diagnostic of the time series, not part of a step).
 """
 from __future__ import annotations
 

@@ -14,7 +14,8 @@ Recipe (nondimensional: lengths in W0, time in W0^2/D_l, c in c_inf):
 * optional seeded perturbation phi += amp (2 xi - 1) 4 phi0 (1 - phi0),
   xi ~ U[0, 1), band-limited to the interface so the bulk stays exactly 0/1;
 * the five workload definitions of the hot path (1D front, 2D and 3D
-  directional solidification, a 256-run k(V) sweep, the adjoint fit runs).
+  directional solidification, a 256-run k(V) sweep, the adjoint fit runs), the
+  1D front at the paper's A = 2 and the solute-band run.
 """
 from __future__ import annotations
 
@@ -149,10 +150,19 @@ def run_dt(V: float, dx: float = DX, alpha: float = 1.0, W: float = 1.0) -> floa
     return min(0.2 * dx * dx, 0.1 * dx / V, 0.4 * alpha * dx * dx / (2.0 * W * W))
 
 
+def front_cell(N: int, V: float, dx: float = DX) -> int:
+    """Initial front cell of a 1D run: the liquid ahead keeps 12 diffusion
+    lengths D_l / V of the solute boundary layer (at least 48 W), and the rest
+    of the window lies behind the front, where a fast front falls back while
+    its kinetic undercooling builds up; never below N/4."""
+    ahead = int(math.ceil(max(48.0, 12.0 / V) / dx))
+    return max(N // 4, N - ahead)
+
+
 def batch_runs(nruns: int = 256, seed: int = 3, nmin: int = 512, nmax: int = 8192,
                vmin_log10: float = -3.0, vmax_log10: float = 1.0):
     """k(V) sweep: velocities log-spaced from 1e-3 to 10, lengths uniform in
-    [512, 8192] (seeded), per-run dt from ``run_dt``, front at N/4.
+    [512, 8192] (seeded), per-run dt from ``run_dt``, front at ``front_cell``.
 
     Returns a list of dicts with keys N, V, dt, z0."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -162,7 +172,7 @@ def batch_runs(nruns: int = 256, seed: int = 3, nmin: int = 512, nmax: int = 819
         frac = r / (nruns - 1) if nruns > 1 else 0.0
         V = 10.0 ** (vmin_log10 + (vmax_log10 - vmin_log10) * frac)
         N = nmin + int(math.floor((nmax - nmin + 1) * xi[r]))
-        runs.append(dict(N=N, V=V, dt=run_dt(V), z0=(N // 4) * DX))
+        runs.append(dict(N=N, V=V, dt=run_dt(V), z0=front_cell(N, V) * DX))
     return runs
 
 

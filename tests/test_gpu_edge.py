@@ -79,7 +79,7 @@ def test_tiny_grids(torch_dev, oracle, dim, n, periodic, model):
     torch = torch_dev
     nz = n[dim - 1]
     p = I.base_params(dim=dim, n=n, periodic=periodic, V=0.5, dt=I.run_dt(0.5) / 4.0, z0=(nz // 3) * I.DX + 0.4,
-                      model=model, eps_grad=1e-4 if model else I.ALLOY["eps_grad"])
+                      model=model)
     f = [a.ravel() for a in I.planar_front(dim, n, p["dx"], p["z0"], p["ke"], amp=0.05, seed=9)]
     steps = 60
     print(f"case: tiny grid dim={dim} n={n} periodic={periodic} model={model}", flush=True)

@@ -45,7 +45,7 @@ def _split_ok(ke, cs, cl):
 
 
 KKS = dict(model=1, A=1.0, b=I.ALLOY["ke"] * I.ALLOY["Ds"])
-EQ12 = dict(model=1, A=1.2, eps_grad=1e-4)
+EQ12 = dict(model=1, A=1.2)
 
 
 @pytest.mark.parametrize("variant", ["kks", "A1.2"])

@@ -298,20 +298,23 @@ def _window(a, x, y, z, w):
 def test_3d_half_billion_cells_sampled(torch_dev, oracle, model):
     """A 1024 x 1024 x 512 grid (5.4e8 cells, 26 GB of fields and twins on
     the device), one step in the production launch configuration.  Sampled
-    windows (periodic wrap in x and y, tile and z edges, the interface) are
+    windows (periodic wrap in x and y, tile and z edges, the seams of the z
+    chunks at 96 and 192 planes, the interface on the first of them) are
     compared with an oracle step of the same window on the cells whose
     dependency cone (radius 2) lies inside it."""
     from paper_2303_09671_amd import pf
     torch = torch_dev
     nx, ny, nz = 1024, 1024, 512
     p, _, pert = I.config_3d()
-    p = dict(p, n=(nx, ny, nz), z0=(nz // 4) * I.DX, model=model, eps_grad=1e-4 if model else p["eps_grad"])
+    # the front sits on the seam of the launch's z chunks (96 planes at this size), so the
+    # windows around it cross the chunk start and end with the interface inside them
+    zi = 96
+    p = dict(p, n=(nx, ny, nz), z0=zi * I.DX, model=model)
     print(f"case: 3D {nx}x{ny}x{nz} one step, model={model}", flush=True)
     phi, cs, cl = I.device_front(nx, ny, nz, p["dx"], p["z0"], p["ke"], 1e-3, 11)
     w = 5
-    zi = nz // 4
     centres = [(0, 0, zi), (31, 7, zi - 1), (32 * 17, 8 * 50 + 7, zi + 2), (nx - 1, ny - 1, zi), (500, 300, 3),
-               (700, 900, nz - 2), (100, 200, zi + 30)]
+               (700, 900, nz - 2), (100, 200, zi + 30), (600, 40, 2 * zi)]
     host0 = {}
     for (x, y, z) in centres:
         lo, hi = max(z - w, 0), min(z + w + 1, nz)
