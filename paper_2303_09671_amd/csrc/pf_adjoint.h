@@ -81,21 +81,31 @@ struct Acc {
   double* apt;
 };
 
-// Scatter helper: adds v at the canonical box position of local coordinates.
+// Canonical box position of the box cell at local coordinates (lx, lz): mirror
+// ghosts folded onto their images (z always; x when not periodic), or -1 when
+// the image lies outside the box.  Tabulated once per block.
 template <int DIM>
-__device__ __forceinline__ void scat(double* a, const Dom& d, int lx, int lz, double v) {
+__device__ __forceinline__ int canonical(const Dom& d, int lx, int lz) {
   using G = Geo<DIM>;
-  if (v == 0.0) return;
-  // fold mirror ghosts onto their images (z always; x when not periodic)
   int gz = d.z0 + lz;
   if (gz < 0 || gz >= d.nz) lz = reflect(gz, d.nz) - d.z0;
   if (DIM == 2 && !d.px) {
     int gx = d.x0 + lx;
     if (gx < 0 || gx >= d.nx) lx = reflect(gx, d.nx) - d.x0;
   }
-  if (lz < -H || lz >= G::TZ + H) return;
-  if (DIM == 2 && (lx < -H || lx >= G::TX + H)) return;
-  atomicAdd(&a[G::idx(lx, lz)], v);
+  if (lz < -H || lz >= G::TZ + H) return -1;
+  if (DIM == 2 && (lx < -H || lx >= G::TX + H)) return -1;
+  return G::idx(lx, lz);
+}
+
+// Scatter helper: adds v at the canonical position of box cell i (every
+// scatter target of the face and cell stages lies inside the box).  2D reads
+// the block's table; 1D folds inline (one axis, cheaper than an LDS read).
+template <int DIM>
+__device__ __forceinline__ void scat(double* a, const Dom& d, const int* canon, int i, double v) {
+  if (v == 0.0) return;
+  const int j = (DIM == 2) ? canon[i] : canonical<1>(d, 0, i - H);
+  if (j >= 0) atomicAdd(&a[j], v);
 }
 
 template <int DIM, bool APZ>
@@ -107,6 +117,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
   // 1D: (mu_s - mu_l)/Omega of the box, computed once (2D: recomputed; no LDS room)
   __shared__ double sdm[(DIM == 1) ? G::NB : 1];
   __shared__ double red[NTH][G::NT / 64];
+  __shared__ int canon[(DIM == 2) ? G::NB : 1];
   const int tid = threadIdx.x;
   const double tn = (double)n * d.dt;
   const double sn = floor(d.V * tn / c.dx);
@@ -130,6 +141,7 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
     amu[i] = 0.0;
     apt[i] = 0.0;
     spt[i] = 0.0;
+    if (DIM == 2) canon[i] = canonical<DIM>(d, lx, lz);
     {  // mu_bar, pointwise: whole box
       double p, q;
       pfk::interp_pq<APZ>(c, su[0][i], p, q);
@@ -310,32 +322,30 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       }
       const double phf_b = (p_b - q_b) * dp;
       // distribute to the cells of the stencil
-      const int axl = lx, azl = lz;
-      scat<DIM>(au[0], d, axl, azl, 0.5 * phf_b - gph_b[K] * c.inv_dx);
-      scat<DIM>(au[0], d, bx, bz, 0.5 * phf_b + gph_b[K] * c.inv_dx);
-      scat<DIM>(au[1], d, axl, azl, 0.5 * csf_b - gcs_b[K] * c.inv_dx);
-      scat<DIM>(au[1], d, bx, bz, 0.5 * csf_b + gcs_b[K] * c.inv_dx);
-      scat<DIM>(au[2], d, axl, azl, 0.5 * clf_b - gcl_b[K] * c.inv_dx);
-      scat<DIM>(au[2], d, bx, bz, 0.5 * clf_b + gcl_b[K] * c.inv_dx);
-      scat<DIM>(amu, d, axl, azl, -gmu_b[K] * c.inv_dx);
-      scat<DIM>(amu, d, bx, bz, gmu_b[K] * c.inv_dx);
-      scat<DIM>(apt, d, axl, azl, 0.5 * ptf_b);
-      scat<DIM>(apt, d, bx, bz, 0.5 * ptf_b);
-      if (DIM == 2) {
-        const int jx = (J == 0) ? 1 : 0, jz = (J == DIM - 1) ? 1 : 0;
+      scat<DIM>(au[0], d, canon, ia, 0.5 * phf_b - gph_b[K] * c.inv_dx);
+      scat<DIM>(au[0], d, canon, ib, 0.5 * phf_b + gph_b[K] * c.inv_dx);
+      scat<DIM>(au[1], d, canon, ia, 0.5 * csf_b - gcs_b[K] * c.inv_dx);
+      scat<DIM>(au[1], d, canon, ib, 0.5 * csf_b + gcs_b[K] * c.inv_dx);
+      scat<DIM>(au[2], d, canon, ia, 0.5 * clf_b - gcl_b[K] * c.inv_dx);
+      scat<DIM>(au[2], d, canon, ib, 0.5 * clf_b + gcl_b[K] * c.inv_dx);
+      scat<DIM>(amu, d, canon, ia, -gmu_b[K] * c.inv_dx);
+      scat<DIM>(amu, d, canon, ib, gmu_b[K] * c.inv_dx);
+      scat<DIM>(apt, d, canon, ia, 0.5 * ptf_b);
+      scat<DIM>(apt, d, canon, ib, 0.5 * ptf_b);
+      if (DIM == 2) {  // transverse neighbours of both cells: box offsets +-oJ
         const double* gb[3] = {&gph_b[J], &gcs_b[J], &gcl_b[J]};
         for (int f = 0; f < 3; ++f) {
           const double v = *gb[f] * c.inv_4dx;
-          scat<DIM>(au[f], d, axl + jx, azl + jz, v);
-          scat<DIM>(au[f], d, axl - jx, azl - jz, -v);
-          scat<DIM>(au[f], d, bx + jx, bz + jz, v);
-          scat<DIM>(au[f], d, bx - jx, bz - jz, -v);
+          scat<DIM>(au[f], d, canon, ia + oJ, v);
+          scat<DIM>(au[f], d, canon, ia - oJ, -v);
+          scat<DIM>(au[f], d, canon, ib + oJ, v);
+          scat<DIM>(au[f], d, canon, ib - oJ, -v);
         }
         const double v = gmu_b[J] * c.inv_4dx;
-        scat<DIM>(amu, d, axl + jx, azl + jz, v);
-        scat<DIM>(amu, d, axl - jx, azl - jz, -v);
-        scat<DIM>(amu, d, bx + jx, bz + jz, v);
-        scat<DIM>(amu, d, bx - jx, bz - jz, -v);
+        scat<DIM>(amu, d, canon, ia + oJ, v);
+        scat<DIM>(amu, d, canon, ia - oJ, -v);
+        scat<DIM>(amu, d, canon, ib + oJ, v);
+        scat<DIM>(amu, d, canon, ib - oJ, -v);
       }
     }
   };
@@ -482,18 +492,18 @@ __device__ void adjoint_tile(const Const& c, const Dom& d, long long n, int shif
       gcs_b[k] = dot_b * c.Ds * gph[k];
       gcl_b[k] = -dot_b * c.b * gph[k];
     }
-    scat<DIM>(au[0], d, lx, lz, ph_b - 2.0 * DIM * lap_b * c.inv_dx2);
-    scat<DIM>(au[1], d, lx, lz, cs_b);
-    scat<DIM>(au[2], d, lx, lz, cl_b);
+    scat<DIM>(au[0], d, canon, i, ph_b - 2.0 * DIM * lap_b * c.inv_dx2);
+    scat<DIM>(au[1], d, canon, i, cs_b);
+    scat<DIM>(au[2], d, canon, i, cl_b);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const int sx = (DIM == 2 && k == 0) ? 1 : 0, sz = (k == DIM - 1) ? 1 : 0;
-      scat<DIM>(au[0], d, lx + sx, lz + sz, gph_b[k] * c.inv_2dx + lap_b * c.inv_dx2);
-      scat<DIM>(au[0], d, lx - sx, lz - sz, -gph_b[k] * c.inv_2dx + lap_b * c.inv_dx2);
-      scat<DIM>(au[1], d, lx + sx, lz + sz, gcs_b[k] * c.inv_2dx);
-      scat<DIM>(au[1], d, lx - sx, lz - sz, -gcs_b[k] * c.inv_2dx);
-      scat<DIM>(au[2], d, lx + sx, lz + sz, gcl_b[k] * c.inv_2dx);
-      scat<DIM>(au[2], d, lx - sx, lz - sz, -gcl_b[k] * c.inv_2dx);
+      const int o = G::off(k);
+      scat<DIM>(au[0], d, canon, i + o, gph_b[k] * c.inv_2dx + lap_b * c.inv_dx2);
+      scat<DIM>(au[0], d, canon, i - o, -gph_b[k] * c.inv_2dx + lap_b * c.inv_dx2);
+      scat<DIM>(au[1], d, canon, i + o, gcs_b[k] * c.inv_2dx);
+      scat<DIM>(au[1], d, canon, i - o, -gcs_b[k] * c.inv_2dx);
+      scat<DIM>(au[2], d, canon, i + o, gcl_b[k] * c.inv_2dx);
+      scat<DIM>(au[2], d, canon, i - o, -gcl_b[k] * c.inv_2dx);
     }
   }
   __syncthreads();
