@@ -379,6 +379,91 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     F0[f] = Fs;
     if constexpr (!EQ) F1[f] = Fl;
   };
+  // 3D: the x and y faces on the low side of the own cell and the z face above
+  // it, from one gather of what they share: the own cell's values (phi, c_s,
+  // c_l, mu_bar) and its central differences along each axis are read from LDS
+  // once and enter two faces each.  Same arithmetic, in the same order, as
+  // face_item and zface.
+  struct F4 {
+    double p, s, l, m;
+  };
+  auto own_faces3 = [&](int gz, double& FsU, double& FlU, F4& own, double& ptown) {
+    const int s0 = slot3(gz), sm = slot3(gz - 1), sp = slot3(gz + 1);
+    const int m0 = (gz + 9) % 3, mm = (gz + 8) % 3, mp = (gz + 10) % 3;
+    const int ic = G::i2(ox, oy), jc = G::i1(ox, oy);
+    constexpr int DY2 = G::BX2, DY1 = G::BX1;
+    auto cen = [&](int sl, int ml, int i, int j) { return F4{su[sl][0][i], CS(sl, i), su[sl][2][i], smu[ml][j]}; };
+    // central difference along an in-plane axis (ring offsets d2, d1)
+    auto dif = [&](int sl, int ml, int i, int j, int d2, int d1) {
+      return F4{su[sl][0][i + d2] - su[sl][0][i - d2], CS(sl, i + d2) - CS(sl, i - d2),
+                su[sl][2][i + d2] - su[sl][2][i - d2], smu[ml][j + d1] - smu[ml][j - d1]};
+    };
+    // central difference along z about plane gz
+    auto difz = [&](int i, int j) {
+      return F4{su[sp][0][i] - su[sm][0][i], CS(sp, i) - CS(sm, i), su[sp][2][i] - su[sm][2][i],
+                smu[mp][j] - smu[mm][j]};
+    };
+    auto add = [](const F4& u, const F4& v) { return F4{u.p + v.p, u.s + v.s, u.l + v.l, u.m + v.m}; };
+    // face normal to K between cells a and b = a + e_K; t1, t2 the transverse
+    // sums along the other two axes in axis order
+    auto face = [&](auto axis, const F4& a, const F4& b, const F4& t1, const F4& t2, double pta, double ptb,
+                    double& Fs, double& Fl) {
+      constexpr int K = decltype(axis)::value;
+      constexpr int J1 = (K == 0) ? 1 : 0, J2 = (K == 2) ? 1 : 2;
+      double gph[3], gmu[3], gcs[3], gcl[3];
+      gph[K] = b.p - a.p;
+      gmu[K] = b.m - a.m;
+      gcs[K] = b.s - a.s;
+      gcl[K] = b.l - a.l;
+      gph[J1] = t1.p;
+      gmu[J1] = t1.m;
+      gcs[J1] = t1.s;
+      gcl[J1] = t1.l;
+      gph[J2] = t2.p;
+      gmu[J2] = t2.m;
+      gcs[J2] = t2.s;
+      gcl[J2] = t2.l;
+      face_flux<3, K, APZ, EQ>(c, 0.5 * (a.p + b.p), 0.5 * (a.s + b.s), 0.5 * (a.l + b.l), 0.5 * (pta + ptb), gph,
+                               gmu, gcs, gcl, Fs, Fl);
+    };
+    auto closed = [&](int g, int n, int per) { return (!per && (g == 0 || g >= n)) || g > n; };
+    const F4 cc = cen(s0, m0, ic, jc);
+    const F4 dzc = difz(ic, jc);
+    const double ptc = spt[(gz + 8) & 1][jc];
+    const F4 dyc = dif(s0, m0, ic, jc, DY2, DY1);
+    {  // x face (a = own cell - e_x)
+      double Fs = 0.0, Fl = 0.0;
+      if (!closed(x0 + ox, nx, c.px)) {
+        const int ia = ic - 1, ja = jc - 1;
+        face(std::integral_constant<int, 0>{}, cen(s0, m0, ia, ja), cc, add(dif(s0, m0, ia, ja, DY2, DY1), dyc),
+             add(difz(ia, ja), dzc), spt[(gz + 8) & 1][ja], ptc, Fs, Fl);
+      }
+      const int f = oy * (TX + 1) + ox;
+      sfx[0][f] = Fs;
+      if constexpr (!EQ) sfx[1][f] = Fl;
+    }
+    const F4 dxc = dif(s0, m0, ic, jc, 1, 1);
+    {  // y face (a = own cell - e_y)
+      double Fs = 0.0, Fl = 0.0;
+      if (!closed(y0 + oy, ny, c.py)) {
+        const int ia = ic - DY2, ja = jc - DY1;
+        face(std::integral_constant<int, 1>{}, cen(s0, m0, ia, ja), cc, add(dif(s0, m0, ia, ja, 1, 1), dxc),
+             add(difz(ia, ja), dzc), spt[(gz + 8) & 1][ja], ptc, Fs, Fl);
+      }
+      const int f = oy * TX + ox;
+      sfy[0][f] = Fs;
+      if constexpr (!EQ) sfy[1][f] = Fl;
+    }
+    own = cc;  // for the update
+    ptown = ptc;
+    FsU = 0.0;
+    FlU = 0.0;
+    if (gz >= 0 && gz + 1 < nz) {  // z face (b = own cell in plane gz + 1)
+      const F4 cu = cen(sp, mp, ic, jc);
+      face(std::integral_constant<int, 2>{}, cc, cu, add(dxc, dif(sp, mp, ic, jc, 1, 1)),
+           add(dyc, dif(sp, mp, ic, jc, DY2, DY1)), ptc, spt[(gz + 9) & 1][jc], FsU, FlU);
+    }
+  };
   // Face items: every thread takes the x and y faces on the low side of its own
   // cell; the faces on the high side of the tile (TY of them in x, TX in y) go
   // to wave 2 (x) and wave 3 (y), as the extra cells of the cell stage go to
@@ -406,26 +491,27 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   for (int z = zb; z < ze; ++z) {
     cell_plane(z + 1, false, false);  // plane z+2 read from global memory
     __syncthreads();
-    if constexpr (DIM == 3) {
-      face_item(std::integral_constant<int, 0>{}, z, ox, oy);
-      face_item(std::integral_constant<int, 1>{}, z, ox, oy);
-    } else if (tid <= TX) {
-      face_item(std::integral_constant<int, 0>{}, z, tid, 0);  // the TX + 1 x faces in one pass
-    }
     double FsU = 0.0, FlU = 0.0;
-    if (own) zface(z, FsU, FlU);
+    F4 ownv{};  // 3D: the own cell's (phi, c_s, c_l) and phi_t, kept for the update
+    double ptv = 0.0;
     if constexpr (DIM == 3) {
       if (extra_f) {  // one call: lanes 0..EX-1 take x faces, the rest y faces
         const int K = (le < EX) ? 0 : 1;
         face_item_rt(K, z, (K == 0) ? TX : le - EX, (K == 0) ? le : TY);
       }
+      own_faces3(z, FsU, FlU, ownv, ptv);
+    } else {
+      if (tid <= TX) face_item(std::integral_constant<int, 0>{}, z, tid, 0);  // the TX + 1 x faces in one pass
+      if (own) zface(z, FsU, FlU);
     }
     __syncthreads();
     if (own_valid) {
       const int s0 = slot3(z);
       const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
-      const double ph = su[s0][0][ic], cs = CS(s0, ic), cl = su[s0][2][ic];
-      const double pt = spt[(z + 8) & 1][i1];
+      const double ph = (DIM == 3) ? ownv.p : su[s0][0][ic];
+      const double cs = (DIM == 3) ? ownv.s : CS(s0, ic);
+      const double cl = (DIM == 3) ? ownv.l : su[s0][2][ic];
+      const double pt = (DIM == 3) ? ptv : spt[(z + 8) & 1][i1];
       double divs = sfx[0][oy * (TX + 1) + ox + 1] - sfx[0][oy * (TX + 1) + ox];
       if (DIM == 3) divs += sfy[0][(oy + 1) * TX + ox] - sfy[0][oy * TX + ox];
       divs += FsU - FsD;
