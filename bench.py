@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="time only the 3D workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-calib", action="store_true", help="run the plain copy used to scale counters")
+    ap.add_argument("--adjoint-only", type=int, default=0, metavar="NSTEPS",
+                    help="time only the adjoint workloads over NSTEPS steps (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -296,6 +298,9 @@ def main():
         copy_calibration()
         return
     import torch
+    if args.adjoint_only > 0:
+        print(json.dumps({"adjoint": bench_adjoint(torch, nsteps=args.adjoint_only)}), flush=True)
+        return
     from paper_2303_09671_amd import inputs as I
     from paper_2303_09671_amd import pf
     assert torch.cuda.is_available(), "bench.py needs a GPU"
