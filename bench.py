@@ -221,6 +221,28 @@ def bench_bands(torch, pf, every=2000):
                 v_I_second_half=[float(v.min()), float(v.mean()), float(v.max())], V_pull=p["V"])
 
 
+def bench_bands_osc(torch, pf, every=125):
+    """The oscillating band run (config_bands_osc: the band workload with the
+    kinetic coefficient alpha = 0.5, N = 8192): front every ``every`` steps;
+    velocity and temperature swings, period and band wavelength over the last
+    two thirds."""
+    from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd.front import front_series, oscillation
+    p, steps = I.config_bands_osc()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    t = [dev(torch, a) for a in f]
+    h = pf.pf_create(p, *t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ser = front_series(h, steps, every, p["dt"])
+    torch.cuda.synchronize()
+    d = time.perf_counter() - t0
+    o = oscillation(ser, t_from=steps * p["dt"] / 3.0)
+    # physical units of the Si-As map: W = 13.5 nm, W^2 / D_l = 1.215e-8 s
+    return dict(cells=p["n"][0], steps=steps, seconds=d, Mphi=p["Mphi"], V_pull=p["V"], **o,
+                period_s=o["period"] * 1.215e-8, wavelength_um=o["wavelength"] * 0.0135)
+
+
 def cpu_baseline(p, pert):
     from oracle import oracle as O
     from paper_2303_09671_amd import inputs as I
@@ -347,6 +369,7 @@ def main():
         extra["batch_256_runs"] = bench_batch(torch, pf, 20000)
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
+        extra["bands_oscillating_1d_8192"] = bench_bands_osc(torch, pf)
         extra["3d_1024x1024x512"] = bench_big(torch, pf, p3)
         # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
         pe = dict(p3, model=1)

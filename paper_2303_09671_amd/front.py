@@ -47,3 +47,20 @@ def _grad_runs(z, t):
     for r in range(z.shape[1]):
         v[:, r] = np.gradient(z[:, r], t[:, r])
     return v
+
+
+def oscillation(ser, run: int = 0, t_from: float = 0.0) -> dict:
+    """Post-processing of a front series (one run) from time ``t_from`` on:
+    range of the interface velocity and temperature, the number of upward
+    crossings of the mean velocity and the mean period between them (NaN
+    with fewer than two), and the band wavelength V_mean x period."""
+    t = ser["t"][:, run]
+    sel = t >= t_from
+    t, v, T = t[sel], ser["v"][sel, run], ser["T"][sel, run]
+    vm = float(np.mean(v))
+    d = v - vm
+    up = np.nonzero((d[:-1] < 0.0) & (d[1:] >= 0.0))[0]
+    period = float(np.mean(np.diff(t[up]))) if len(up) >= 2 else float("nan")
+    return dict(v_min=float(v.min()), v_mean=vm, v_max=float(v.max()), T_min=float(T.min()),
+                T_mean=float(np.mean(T)), T_max=float(T.max()), crossings=int(len(up)), period=period,
+                wavelength=vm * period)

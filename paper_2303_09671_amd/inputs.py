@@ -144,6 +144,19 @@ def config_bands(N: int = 2048, steps: int = 200000):
     return p, steps
 
 
+def config_bands_osc(N: int = 8192, t_end: float = 60000.0):
+    """The band run with the kinetic coefficient lowered to alpha = W / M_phi
+    = 0.5 (M_phi = 2), below the threshold (alpha ~ 0.6 at these parameters)
+    where the planar front turns oscillatory: the oscillatory instability of
+    Sec. V.F.  Everything else as config_bands; a window of N = 8192 cells
+    (front at N/4) holds the front through the swings of T_I, dt from the
+    phi-relaxation limit at that alpha, t_end = 60000 (about 3.6 thermal
+    times l_T / V)."""
+    p, _ = config_bands(N=N)
+    p.update(Mphi=2.0, dt=run_dt(p["V"], alpha=p["W"] / 2.0, W=p["W"]), z0=(N // 4) * DX)
+    return p, int(round(t_end / p["dt"]))
+
+
 def run_dt(V: float, dx: float = DX, alpha: float = 1.0, W: float = 1.0) -> float:
     """Per-run time step from the run's stability limits (diffusion, window
     advection, phi relaxation)."""

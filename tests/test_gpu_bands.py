@@ -1,7 +1,9 @@
 """The solute-band workload (Figs. 8-9 parameters, Si-9%As at G = 1.4e6 K/m,
 v_p = 0.3 m/s): a prefix of the long 1D run against the oracle at the usual
 1e-10, with the front diagnostic on the same state; and the front time series
-helper reading a front that follows the pulling speed."""
+helper reading a front that follows the pulling speed.  The oscillating
+variant (kinetic coefficient alpha = 0.5): a prefix against the oracle, and
+the full run, whose planar front swings periodically (Sec. V.F)."""
 import numpy as np
 import pytest
 
@@ -34,3 +36,42 @@ def test_bands_prefix(oracle):
     # the front advances with the pulling speed to within 20 % over the prefix
     v = (ser["z"][-1, 0] - ser["z"][1, 0]) / (ser["t"][-1, 0] - ser["t"][1, 0])
     assert abs(v - p["V"]) <= 0.2 * p["V"], v
+
+
+def test_band_oscillation_prefix(oracle):
+    import torch
+    from paper_2303_09671_amd import pf
+    p, _ = I.config_bands_osc()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f]
+    h = pf.pf_create(p, *t)
+    steps = 1500
+    print(f"case: oscillating band run prefix {steps} steps, N = {p['n'][0]}", flush=True)
+    pf.pf_step(h, steps)
+    torch.cuda.synchronize()
+    g = [x.cpu().numpy() for x in t]
+    ref = oracle.step(oracle_params(oracle, p), *f, steps)
+    assert_parity(g, ref[:3], what="oscillating band prefix")
+
+
+def test_band_oscillation_full_run():
+    """The full oscillating run: the front velocity swings between a near stop
+    and several times the pulling speed, periodically, while its mean follows
+    the pulling speed; the interface temperature swings with it."""
+    import torch
+    from paper_2303_09671_amd import pf
+    from paper_2303_09671_amd.front import front_series, oscillation
+    p, steps = I.config_bands_osc()
+    f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f]
+    h = pf.pf_create(p, *t)
+    print(f"case: oscillating band run, {steps} steps, N = {p['n'][0]}", flush=True)
+    ser = front_series(h, steps, 125, p["dt"])
+    assert pf.pf_check(h) == pf.PF_OK
+    assert np.isfinite(ser["z"]).all()
+    o = oscillation(ser, t_from=steps * p["dt"] / 3.0)
+    print(f"  {o}", flush=True)
+    V = p["V"]
+    assert abs(o["v_mean"] - V) < 0.05 * V
+    assert o["v_max"] > 2.0 * V and o["v_min"] < 0.5 * V
+    assert o["crossings"] >= 2 and o["T_max"] - o["T_min"] > 0.1
