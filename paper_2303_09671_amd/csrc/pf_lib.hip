@@ -436,7 +436,9 @@ int pf_create(const pf_params* p, double* phi, double* cs, double* cl, void* str
       h->zchunk = std::min(zchunk_for(c.nz, tiles, 11LL * ncu, 16), 96);
     } else {
       const long long tiles = (c.nx + S2_TX - 1) / S2_TX;
-      h->zchunk = zchunk_for(c.nz, tiles, 32LL * ncu, 4);  // chunks of 4 planes at 1024^2 (measured best)
+      // about 13 one-wave workgroups per CU: chunks of 6 planes at 1024^2 (measured: 6 planes
+      // 30.1 us per step, 4: 33.4, 5: 31.1, 7: 31.7, 8: 35.0)
+      h->zchunk = zchunk_for(c.nz, tiles, 13LL * ncu, 4);
     }
     if (const char* e = std::getenv("PF_ZCHUNK")) {  // tuning override
       const int v = std::atoi(e);
