@@ -221,14 +221,15 @@ def bench_bands(torch, pf, every=2000):
                 v_I_second_half=[float(v.min()), float(v.mean()), float(v.max())], V_pull=p["V"])
 
 
-def bench_bands_osc(torch, pf, every=125):
+def bench_bands_osc(torch, pf, every=125, g_factor=1.0):
     """The oscillating band run (config_bands_osc: the band workload with the
-    kinetic coefficient alpha = 0.5, N = 8192): front every ``every`` steps;
-    velocity and temperature swings, period and band wavelength over the last
-    two thirds."""
+    kinetic coefficient alpha = 0.5, N = 8192), with the temperature gradient
+    scaled by ``g_factor``: front every ``every`` steps; velocity and
+    temperature swings, period and band wavelength over the last two thirds."""
     from paper_2303_09671_amd import inputs as I
     from paper_2303_09671_amd.front import front_series, oscillation
     p, steps = I.config_bands_osc()
+    p["inv_lT"] *= g_factor
     f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
     t = [dev(torch, a) for a in f]
     h = pf.pf_create(p, *t)
@@ -239,8 +240,8 @@ def bench_bands_osc(torch, pf, every=125):
     d = time.perf_counter() - t0
     o = oscillation(ser, t_from=steps * p["dt"] / 3.0)
     # physical units of the Si-As map: W = 13.5 nm, W^2 / D_l = 1.215e-8 s
-    return dict(cells=p["n"][0], steps=steps, seconds=d, Mphi=p["Mphi"], V_pull=p["V"], **o,
-                period_s=o["period"] * 1.215e-8, wavelength_um=o["wavelength"] * 0.0135)
+    return dict(cells=p["n"][0], steps=steps, seconds=d, Mphi=p["Mphi"], V_pull=p["V"], G_K_per_m=1.4e6 * g_factor,
+                **o, period_s=o["period"] * 1.215e-8, wavelength_um=o["wavelength"] * 0.0135)
 
 
 def cpu_baseline(p, pert):
@@ -370,6 +371,7 @@ def main():
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
         extra["bands_oscillating_1d_8192"] = bench_bands_osc(torch, pf)
+        extra["bands_oscillating_1d_8192_G_1.4e7"] = bench_bands_osc(torch, pf, g_factor=10.0)
         extra["3d_1024x1024x512"] = bench_big(torch, pf, p3)
         # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
         pe = dict(p3, model=1)

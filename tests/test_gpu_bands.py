@@ -4,6 +4,8 @@ v_p = 0.3 m/s): a prefix of the long 1D run against the oracle at the usual
 helper reading a front that follows the pulling speed.  The oscillating
 variant (kinetic coefficient alpha = 0.5): a prefix against the oracle, and
 the full run, whose planar front swings periodically (Sec. V.F)."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -54,24 +56,41 @@ def test_band_oscillation_prefix(oracle):
     assert_parity(g, ref[:3], what="oscillating band prefix")
 
 
-def test_band_oscillation_full_run():
-    """The full oscillating run: the front velocity swings between a near stop
-    and several times the pulling speed, periodically, while its mean follows
-    the pulling speed; the interface temperature swings with it."""
+@functools.lru_cache(maxsize=None)  # one run per gradient for the tests below
+def _oscillating_run(g_factor):
     import torch
     from paper_2303_09671_amd import pf
     from paper_2303_09671_amd.front import front_series, oscillation
     p, steps = I.config_bands_osc()
+    p["inv_lT"] *= g_factor
     f = I.planar_front(1, p["n"], p["dx"], p["z0"], p["ke"])
     t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f]
     h = pf.pf_create(p, *t)
-    print(f"case: oscillating band run, {steps} steps, N = {p['n'][0]}", flush=True)
+    print(f"case: oscillating band run, G x {g_factor}, {steps} steps, N = {p['n'][0]}", flush=True)
     ser = front_series(h, steps, 125, p["dt"])
     assert pf.pf_check(h) == pf.PF_OK
     assert np.isfinite(ser["z"]).all()
     o = oscillation(ser, t_from=steps * p["dt"] / 3.0)
     print(f"  {o}", flush=True)
+    return p, o
+
+
+def test_band_oscillation_full_run():
+    """The full oscillating run: the front velocity swings between a near stop
+    and several times the pulling speed, periodically, while its mean follows
+    the pulling speed; the interface temperature swings with it."""
+    p, o = _oscillating_run(1.0)
     V = p["V"]
     assert abs(o["v_mean"] - V) < 0.05 * V
     assert o["v_max"] > 2.0 * V and o["v_min"] < 0.5 * V
     assert o["crossings"] >= 2 and o["T_max"] - o["T_min"] > 0.1
+
+
+def test_band_wavelength_falls_with_gradient():
+    """Ten times the temperature gradient (Table 1's G = 1.4e7 K/m): the front
+    still oscillates about the pulling speed, with a band wavelength several
+    times shorter (the trend of Fig. 9(c))."""
+    p, o1 = _oscillating_run(1.0)
+    _, o10 = _oscillating_run(10.0)
+    assert abs(o10["v_mean"] - p["V"]) < 0.05 * p["V"] and o10["crossings"] >= 10
+    assert o10["wavelength"] < o1["wavelength"] / 3.0
