@@ -38,6 +38,8 @@ BYTES_PER_CELL = 48.0      # read and write phi, c_s, c_l (FP64)
 BYTES_PER_CELL_EQ = 40.0   # equal-potential model: read phi, c_l; write phi, c_s, c_l
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream3d_256_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_09671_amd", "csrc", f) for f in ("pf_device.h", "pf_kernels.h")]
+# the build flags enter the hash too: a record stays valid only for the same compiled kernel
+KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2303_09671_amd", "build.py"))
 
 
 def kernel_source_hash() -> str:
