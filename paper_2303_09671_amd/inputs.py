@@ -144,16 +144,17 @@ def config_bands(N: int = 2048, steps: int = 200000):
     return p, steps
 
 
-def config_bands_osc(N: int = 8192, t_end: float = 60000.0):
+def config_bands_osc(N: int = 8192, t_end: float = 60000.0, dx: float = 0.5):
     """The band run with the kinetic coefficient lowered to alpha = W / M_phi
-    = 0.5 (M_phi = 2), below the threshold (alpha ~ 0.6 at these parameters)
-    where the planar front turns oscillatory: the oscillatory instability of
-    Sec. V.F.  Everything else as config_bands; a window of N = 8192 cells
-    (front at N/4) holds the front through the swings of T_I, dt from the
-    phi-relaxation limit at that alpha, t_end = 60000 (about 3.6 thermal
+    = 0.5 (M_phi = 2), below the threshold where the planar front turns
+    oscillatory: the oscillatory instability of Sec. V.F.  Everything else as
+    config_bands, on the paper's main grid spacing dx = 0.5 W (the oscillation
+    is grid-converged from dx = 0.5 on, not at 0.8); a window of N = 8192
+    cells (front at N/4) holds the front through the swings of T_I, dt from
+    the phi-relaxation limit at that alpha, t_end = 60000 (about 3.6 thermal
     times l_T / V)."""
     p, _ = config_bands(N=N)
-    p.update(Mphi=2.0, dt=run_dt(p["V"], alpha=p["W"] / 2.0, W=p["W"]), z0=(N // 4) * DX)
+    p.update(dx=dx, Mphi=2.0, dt=run_dt(p["V"], dx=dx, alpha=p["W"] / 2.0, W=p["W"]), z0=(N // 4) * dx)
     return p, int(round(t_end / p["dt"]))
 
 
