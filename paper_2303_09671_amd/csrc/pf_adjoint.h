@@ -42,15 +42,18 @@ __device__ __forceinline__ void interp2(const Const& c, double phi, double& p, d
 }
 
 // Tile geometry: DIM = 1 (growth axis only) or 2 (x transverse, z growth).
+// 1D: threads per workgroup = cells of the box (tile + halo 3 on each side)
+constexpr int ADJ1_NT = 256;
+
 template <int DIM>
 struct Geo {
   static constexpr int TX = (DIM == 2) ? 16 : 1;
-  static constexpr int TZ = (DIM == 2) ? 16 : 250;  // 1D: box of 256 cells, one per thread
+  static constexpr int TZ = (DIM == 2) ? 16 : ADJ1_NT - 2 * H;  // 1D: one box cell per thread
   static constexpr int BX = (DIM == 2) ? TX + 2 * H : 1;
   static constexpr int BZ = TZ + 2 * H;
   static constexpr int NB = BX * BZ;
   static constexpr int HX = (DIM == 2) ? H : 0;
-  static constexpr int NT = 256;
+  static constexpr int NT = (DIM == 2) ? 256 : ADJ1_NT;
   // box index of local coordinates (lx, lz) relative to the tile origin
   __device__ static __forceinline__ int idx(int lx, int lz) { return (lx + HX) + BX * (lz + H); }
   // unit offset along axis a (0 = x in 2D, DIM-1 = z)
@@ -562,7 +565,7 @@ struct Tile1 {
 };
 
 template <bool APZ>
-__global__ __launch_bounds__(256) void k_adj1d(Const c, pfk::RunTab rt, const Tile1* __restrict__ tiles, long long n,
+__global__ __launch_bounds__(ADJ1_NT) void k_adj1d(Const c, pfk::RunTab rt, const Tile1* __restrict__ tiles, long long n,
                                                int do_shift, const double* u0, const double* u1, const double* u2,
                                                const double* l0, const double* l1, const double* l2, double* o0,
                                                double* o1, double* o2, double* __restrict__ part, int accum) {

@@ -714,7 +714,7 @@ static int adj_launch(pf_handle* h, int64_t n, const double* const u_n[3], const
   const bool apz = (c.ap == 0.0);
   if (h->batched) {
     auto k = apz ? pfadj::k_adj1d<true> : pfadj::k_adj1d<false>;
-    hipLaunchKernelGGL(k, dim3(nblk), dim3(256), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n, h->p.shift,
+    hipLaunchKernelGGL(k, dim3(nblk), dim3(pfadj::ADJ1_NT), 0, h->stream, c, h->runtab(), h->d_tiles, (long long)n, h->p.shift,
                        u_n[0], u_n[1], u_n[2], lam_np1[0], lam_np1[1], lam_np1[2], lam_n[0], lam_n[1], lam_n[2],
                        h->d_theta_part, accum);
   } else {
