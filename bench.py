@@ -246,6 +246,33 @@ def bench_bands_osc(torch, pf, g_factor=1.0):
                 **o, period_s=o["period"] * 1.215e-8, wavelength_um=o["wavelength"] * 0.0135)
 
 
+def bench_ti_curve(torch, pf, A, tail=4000):
+    """T_I and k against the pulling speed in the Fig. 4 setting
+    (config_ti_curve): one batched launch; per run k = 1/c_max, T_I from the
+    front, and whether the front is steady (velocity over ``tail`` further
+    steps within 2 % of V, post-processing of two pf_front readings)."""
+    from paper_2303_09671_amd import inputs as I
+    base, runs, steps, vp = I.config_ti_curve(A)
+    phi, cs, cl, offs = I.batch_fields(runs, ke=base["ke"])
+    t = [dev(torch, a) for a in (phi, cs, cl)]
+    h = pf.pf_create(base, *t, runs=runs, offsets=offs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pf.pf_step(h, steps)
+    f0 = pf.pf_front(h)
+    pf.pf_step(h, tail)
+    f1 = pf.pf_front(h)
+    torch.cuda.synchronize()
+    d = time.perf_counter() - t0
+    _, cm, _ = pf.pf_solute(h)
+    V = np.array([r["V"] for r in runs])
+    dts = np.array([r["dt"] for r in runs])
+    v = (f1["z"] - f0["z"]) / (tail * dts)
+    steady = (f1["ncol"] == 1) & (np.abs(v / V - 1.0) < 0.02)
+    return dict(A=A, runs=len(runs), steps=steps, seconds=d, v_p_m_per_s=[float(x) for x in vp],
+                k=[float(1.0 / x) for x in cm], T_I=[float(x) for x in f1["T"]], steady=[bool(x) for x in steady])
+
+
 def cpu_baseline(p, pert):
     from oracle import oracle as O
     from paper_2303_09671_amd import inputs as I
@@ -373,6 +400,7 @@ def main():
         extra["adjoint"] = bench_adjoint(torch)
         extra["bands_1d_2048"] = bench_bands(torch, pf)
         extra["bands_oscillating_1d_8192"] = bench_bands_osc(torch, pf)
+        extra["ti_curve_fig4"] = [bench_ti_curve(torch, pf, A) for A in (1.2, 2.0)]
         extra["3d_1024x1024x512"] = bench_big(torch, pf, p3)
         # the equal-potential model (mu_s = mu_l imposed) on the 3D and 1D workloads
         pe = dict(p3, model=1)

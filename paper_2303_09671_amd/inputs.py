@@ -158,6 +158,26 @@ def config_bands_osc(N: int = 8192, t_end: float = 60000.0, dx: float = 0.5):
     return p, int(round(t_end / p["dt"]))
 
 
+def config_ti_curve(A: float, N: int = 2048, nruns: int = 24, steps: int = 600000):
+    """Interface temperature and k against the pulling speed in the setting of
+    Fig. 4 (Sec. V.C): Si-9%As (k_e = 0.3, D_l = 1.5e-8 m^2/s, dT0 = 84 K) at
+    W = 13.5 nm, D_s/D_l = 0.1, b = 1, G = 1.4e7 K/m (l_T = dT0 / G = 6 um =
+    444.4 W), lambda0 = I k_e / (1 - k_e)^2, source coefficient A; one batch of
+    ``nruns`` 1D runs with v_p log-spaced from 0.02 to 1 m/s (V = v_p W / D_l),
+    N cells each, the front in mid-window (T_I moves it by up to a few
+    hundred W), dt = min(0.2 dx^2, run_dt(V)), ``steps`` steps (about 1.7
+    thermal times l_T / V at 0.02 m/s).  Returns (base params, runs, steps,
+    v_p in m/s)."""
+    I0 = 1.0 / (3.0 * math.sqrt(2.0))
+    ke = 0.3
+    vp = np.geomspace(0.02, 1.0, nruns)
+    runs = [dict(N=N, V=float(v * 13.5e-9 / 1.5e-8), dt=float(min(0.2 * DX * DX, run_dt(v * 13.5e-9 / 1.5e-8))),
+                 z0=(N // 2) * DX) for v in vp]
+    base = base_params(dim=1)
+    base.update(ke=ke, Ds=0.1, b=1.0, A=A, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=13.5e-9 * 1.4e7 / 84.0)
+    return base, runs, steps, vp
+
+
 def run_dt(V: float, dx: float = DX, alpha: float = 1.0, W: float = 1.0) -> float:
     """Per-run time step from the run's stability limits (diffusion, window
     advection, phi relaxation)."""

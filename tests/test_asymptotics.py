@@ -213,3 +213,14 @@ def test_band_workload_matches_table1_map():
     assert abs(p["V"] - s["V"]) < 1e-12 and p["ke"] == s["ke"]
     assert abs(p["inv_lT"] - s["inv_lT"]) < 1e-3 * s["inv_lT"]  # l_T rounded to 4444 W
     assert abs(p["lambda0"] - s["lambda0"]) < 1e-15
+
+
+def test_ti_curve_workload_matches_table1_map():
+    """The T_I(V) workload is the Table 1 alloy Si-9%As at W = 13.5 nm and
+    G = 1.4e7 K/m mapped to the library's units."""
+    from paper_2303_09671_amd import inputs as I
+    base, runs, _, vp = I.config_ti_curve(1.2)
+    s = asy.nondim("Si-9As", 13.5e-9, vp, G=1.4e7)
+    assert np.allclose([r["V"] for r in runs], s["V"], rtol=1e-12, atol=0.0) and base["ke"] == s["ke"]
+    assert abs(base["inv_lT"] - s["inv_lT"]) < 1e-12 * s["inv_lT"]
+    assert abs(base["lambda0"] - s["lambda0"]) < 1e-15
