@@ -269,8 +269,12 @@ def bench_ti_curve(torch, pf, A, tail=4000):
     dts = np.array([r["dt"] for r in runs])
     v = (f1["z"] - f0["z"]) / (tail * dts)
     steady = (f1["ncol"] == 1) & (np.abs(v / V - 1.0) < 0.02)
+    # the first-order asymptotic k of Eq. partition1 at the same speeds (host side)
+    from paper_2303_09671_amd import asymptotics as asy
+    k_asy, _ = asy.kv_curve(V, A=A, b=base["b"], m=base["Ds"], ke=base["ke"])
     return dict(A=A, runs=len(runs), steps=steps, seconds=d, v_p_m_per_s=[float(x) for x in vp],
-                k=[float(1.0 / x) for x in cm], T_I=[float(x) for x in f1["T"]], steady=[bool(x) for x in steady])
+                k=[float(1.0 / x) for x in cm], k_asymptotic=[float(x) for x in k_asy],
+                T_I=[float(x) for x in f1["T"]], steady=[bool(x) for x in steady])
 
 
 def cpu_baseline(p, pert):
