@@ -41,8 +41,9 @@ __device__ __forceinline__ int map_axis(int g, int n, int periodic) {
 // and kept in 2- and 3-plane rings; x/y face fluxes go through LDS and the
 // z-face flux below a cell stays in a register for the next plane.  One HBM read
 // and one HBM write of the three fields per cell and step, plus halo re-reads
-// (mostly L2 hits).  With a window shift the updated plane z is stored at z-1
-// and the fresh liquid layer at the top.
+// (mostly L2 hits); the ring planes are loaded by LDS DMA.  With a window
+// shift the updated plane z is stored at z-1 and the fresh liquid layer at the
+// top.
 // ---------------------------------------------------------------------------
 // 3D: one thread per tile column (TX * TY threads).  2D: one wave covers the
 // tile (TX = 62 columns) plus its two halo columns, so the cell stage of the
@@ -104,7 +105,6 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   // bank conflicts), item 1 one of the NP1 - NT halo cells (the rows below and
   // above the tile, then the columns left and right), taken by the first
   // threads.
-  constexpr int NLD = (G::P2 + G::NT - 1) / G::NT;
   constexpr int NCS = 2;
   constexpr int NHALO = G::P1 - G::NT;
   static_assert(DIM == 2 ? NHALO == 0 : (NHALO > 0 && NHALO <= G::NT),
@@ -133,18 +133,9 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     return tid < NHALO;
   };
 
-  // In-plane global offsets of this thread's ring positions and cell-stage
-  // positions (the same for every plane), computed once.
-  int ld_off[NLD], cs_off[NCS];  // x + nx y (a plane holds fewer than 2^31 cells)
-#pragma unroll
-  for (int r = 0; r < NLD; ++r) {
-    const int i = min(tid + r * G::NT, G::P2 - 1);
-    const int lx = i % G::BX2 - 2;
-    const int ly = i / G::BX2 - G::OY2;
-    const int gx = map_axis(x0 + lx, nx, c.px);
-    const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
-    ld_off[r] = gx + nx * gy;
-  }
+  // In-plane global offsets of this thread's cell-stage positions (the same
+  // for every plane), computed once.
+  int cs_off[NCS];  // x + nx y (a plane holds fewer than 2^31 cells)
 #pragma unroll
   for (int r = 0; r < NCS; ++r) {
     int lx, ly;
@@ -159,23 +150,54 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
   auto at = [](const double* base, unsigned cell) -> double {
     return *(const double*)((const char*)base + cell * 8u);
   };
-  auto load_plane = [&](int gz) {
-    const int slot = slot3(gz);
-    const long long zo = plane * mirror_idx(gz, nz);
-    const double* bph = iph + zo;
-    const double* bcs = ics + zo;
-    const double* bcl = icl + zo;
+  // Ring loads go from global memory straight into LDS (global_load_lds, 16
+  // bytes a lane, no registers on the way): thread k moves ring positions 2k
+  // and 2k+1 of each field when they are adjacent and 16-byte aligned in
+  // global memory; the other pairs (mirror images at a non-periodic x edge,
+  // periodic wraps inside a pair, odd plane sizes, unaligned bases) go through
+  // registers.  The hardware writes lane l of a wave at the wave's LDS base +
+  // 16 l, so the base passed is the ring position of the wave's first pair.
+  // Issued after the face stage, the loads land while the update runs; each
+  // wave waits for its own with dma_wait before the barrier that publishes the
+  // plane.
+  constexpr int NCH = G::P2 / 2;
+  static_assert(G::P2 % 2 == 0 && NCH <= G::NT, "tile shape: ring pairs must fit one per thread");
+  int pr_off[2];  // in-plane cell indices of ring positions 2k, 2k+1
 #pragma unroll
-    for (int r = 0; r < NLD; ++r) {
-      const int i = tid + r * G::NT;
-      if (i < G::P2) {
-        const unsigned o = (unsigned)ld_off[r];
-        su[slot][0][i] = at(bph, o);
-        if constexpr (!EQ) su[slot][1][i] = at(bcs, o);
-        su[slot][2][i] = at(bcl, o);
+  for (int q = 0; q < 2; ++q) {
+    const int i = 2 * min(tid, NCH - 1) + q;
+    const int lx = i % G::BX2 - 2;
+    const int ly = i / G::BX2 - G::OY2;
+    const int gx = map_axis(x0 + lx, nx, c.px);
+    const int gy = (DIM == 3) ? map_axis(y0 + ly, ny, c.py) : 0;
+    pr_off[q] = gx + nx * gy;
+  }
+  const bool al16 =
+      (((unsigned long long)iph | (unsigned long long)icl | (EQ ? 0ull : (unsigned long long)ics)) & 15ull) == 0;
+  const int podd = (int)(plane & 1);
+  const int wch = __builtin_amdgcn_readfirstlane(tid & ~63);  // first pair of this wave
+  auto load_plane = [&](int gz) {
+    if (tid >= NCH) return;
+    const int slot = slot3(gz);
+    const int gm = mirror_idx(gz, nz);
+    const long long zo = plane * gm;
+    const bool nice = al16 && pr_off[1] == pr_off[0] + 1 && (((podd & gm) + pr_off[0]) & 1) == 0;
+    auto one = [&](const double* in, double* ring) {
+      const double* b = in + zo;
+      if (nice) {
+        __builtin_amdgcn_global_load_lds((const void*)((const char*)b + (unsigned)pr_off[0] * 8u),
+                                         (__attribute__((address_space(3))) void*)(ring + 2 * wch), 16, 0, 0);
+      } else {
+        ring[2 * tid] = at(b, (unsigned)pr_off[0]);
+        ring[2 * tid + 1] = at(b, (unsigned)pr_off[1]);
       }
-    }
+    };
+    one(iph, su[slot][0]);
+    if constexpr (!EQ) one(ics, su[slot][1]);
+    one(icl, su[slot][2]);
   };
+  // vmcnt(0): every global_load_lds of this wave has written LDS
+  auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
 
   // phi_t and mu_bar of plane gz on the tile plus in-plane halo 1.  Planes gz
   // and gz-1 are in the ring; the plane above comes from the ring when
@@ -480,6 +502,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
 
   // ---- prologue: ring = planes zb-1, zb, zb+1; rates of planes zb-1 and zb
   for (int g = zb - 1; g <= zb + 1; ++g) load_plane(g);
+  dma_wait();
   __syncthreads();
   cell_plane(zb - 1, true, true);
   cell_plane(zb, true, false);
@@ -505,6 +528,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
       if (own) zface(z, FsU, FlU);
     }
     __syncthreads();
+    load_plane(z + 2);  // into the slot of plane z-1 (no longer read); lands during the update
     if (own_valid) {
       const int s0 = slot3(z);
       const int ic = G::i2(ox, oy), i1 = G::i1(ox, oy);
@@ -553,7 +577,7 @@ __global__ __launch_bounds__((DIM == 2) ? TX + 2 : TX * TY, (DIM == 3) ? 3 : 1) 
     }
     FsD = FsU;
     FlD = FlU;
-    load_plane(z + 2);  // into the slot of plane z-1 (no longer read)
+    dma_wait();
     __syncthreads();
   }
   if (errbits) atomicOr(err, errbits);
