@@ -246,35 +246,49 @@ def bench_bands_osc(torch, pf, g_factor=1.0):
                 **o, period_s=o["period"] * 1.215e-8, wavelength_um=o["wavelength"] * 0.0135)
 
 
-def bench_ti_curve(torch, pf, A, tail=4000):
+def bench_ti_curve(torch, pf, A, every=5000):
     """T_I and k against the pulling speed in the Fig. 4 setting
-    (config_ti_curve): one batched launch; per run k = 1/c_max, T_I from the
-    front, and whether the front is steady (velocity over ``tail`` further
-    steps within 2 % of V, post-processing of two pf_front readings)."""
+    (config_ti_curve): the batch stepped in launches of ``every`` steps with a
+    pf_front reading after each; per run k = 1/c_max at the end, T_I at the
+    end, and over the last third of the run the front's state (steady,
+    oscillating or transient: front_state), the range of the interface
+    velocity over V and the mean and range of T_I (post-processing of the
+    pf_front readings)."""
     from paper_2303_09671_amd import inputs as I
+    from paper_2303_09671_amd import asymptotics as asy
+    from paper_2303_09671_amd.front import front_series, front_state, oscillation
     base, runs, steps, vp = I.config_ti_curve(A)
     phi, cs, cl, offs = I.batch_fields(runs, ke=base["ke"])
     t = [dev(torch, a) for a in (phi, cs, cl)]
     h = pf.pf_create(base, *t, runs=runs, offsets=offs)
+    V = np.array([r["V"] for r in runs])
+    dts = np.array([r["dt"] for r in runs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pf.pf_step(h, steps)
-    f0 = pf.pf_front(h)
-    pf.pf_step(h, tail)
-    f1 = pf.pf_front(h)
+    ser = front_series(h, steps, every, dts)
     torch.cuda.synchronize()
     d = time.perf_counter() - t0
     _, cm, _ = pf.pf_solute(h)
-    V = np.array([r["V"] for r in runs])
-    dts = np.array([r["dt"] for r in runs])
-    v = (f1["z"] - f0["z"]) / (tail * dts)
-    steady = (f1["ncol"] == 1) & (np.abs(v / V - 1.0) < 0.02)
+    ncol = pf.pf_front(h)["ncol"]
+    state, osc = [], []
+    for i in range(len(runs)):
+        t_from = steps * dts[i] * 2.0 / 3.0
+        state.append(front_state(ser, i, V[i], t_from) if ncol[i] == 1 else "no single front")
+        osc.append(oscillation(ser, i, t_from))
     # the first-order asymptotic k of Eq. partition1 at the same speeds (host side)
-    from paper_2303_09671_amd import asymptotics as asy
     k_asy, _ = asy.kv_curve(V, A=A, b=base["b"], m=base["Ds"], ke=base["ke"])
-    return dict(A=A, runs=len(runs), steps=steps, seconds=d, v_p_m_per_s=[float(x) for x in vp],
-                k=[float(1.0 / x) for x in cm], k_asymptotic=[float(x) for x in k_asy],
-                T_I=[float(x) for x in f1["T"]], steady=[bool(x) for x in steady])
+    f = lambda xs: [float(x) for x in xs]
+    return dict(A=A, runs=len(runs), steps=steps, front_every=every, seconds=d, v_p_m_per_s=f(vp),
+                k=f(1.0 / cm), k_asymptotic=f(k_asy), T_I=f(ser["T"][-1]),
+                T_I_last_third_mean=f(o["T_mean"] for o in osc), T_I_last_third_min=f(o["T_min"] for o in osc),
+                T_I_last_third_max=f(o["T_max"] for o in osc),
+                v_over_V_last_third_min=f(o["v_min"] / v for o, v in zip(osc, V)),
+                v_over_V_last_third_max=f(o["v_max"] / v for o, v in zip(osc, V)),
+                state=state, steady=[s == "steady" for s in state],
+                # oscillating fronts: mean period between upward crossings of the mean velocity and
+                # the band wavelength, in the Si-As units (W^2/D_l = 1.215e-8 s, W = 13.5 nm)
+                period_us=[o["period"] * 1.215e-2 if s == "oscillating" else None for o, s in zip(osc, state)],
+                wavelength_um=[o["wavelength"] * 0.0135 if s == "oscillating" else None for o, s in zip(osc, state)])
 
 
 def cpu_baseline(p, pert):

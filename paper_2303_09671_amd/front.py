@@ -64,3 +64,23 @@ def oscillation(ser, run: int = 0, t_from: float = 0.0) -> dict:
     return dict(v_min=float(v.min()), v_mean=vm, v_max=float(v.max()), T_min=float(T.min()),
                 T_mean=float(np.mean(T)), T_max=float(T.max()), crossings=int(len(up)), period=period,
                 wavelength=vm * period)
+
+
+def front_state(ser, run: int, V: float, t_from: float = 0.0, tol: float = 0.02) -> str:
+    """Classify a run's front from time ``t_from`` on (post-processing of a
+    front series): "steady" when the interface velocity stays within ``tol``
+    of the pulling speed V; "oscillating" when it swings by more than that
+    around its mean, crosses the mean upwards at least twice and the largest
+    deviation from V in the second half of the window is at least half of
+    that in the first (a sustained oscillation); "transient" otherwise (a
+    slow or damped approach to V, or drift)."""
+    o = oscillation(ser, run, t_from)
+    if max(abs(o["v_min"] / V - 1.0), abs(o["v_max"] / V - 1.0)) < tol:
+        return "steady"
+    t = ser["t"][:, run]
+    dv = np.abs(ser["v"][t >= t_from, run] - V)
+    h = len(dv) // 2
+    sustained = h > 0 and dv[h:].max() >= 0.5 * dv[:h].max()
+    if o["crossings"] >= 2 and (o["v_max"] - o["v_min"]) > 2.0 * tol * V and sustained:
+        return "oscillating"
+    return "transient"
