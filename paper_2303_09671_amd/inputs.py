@@ -158,7 +158,7 @@ def config_bands_osc(N: int = 8192, t_end: float = 60000.0, dx: float = 0.5):
     return p, int(round(t_end / p["dt"]))
 
 
-def config_ti_curve(A: float, N: int = 2048, nruns: int = 24, steps: int = 600000):
+def config_ti_curve(A: float, N: int = 0, nruns: int = 24, steps: int = 0, dx: float = DX):
     """Interface temperature and k against the pulling speed in the setting of
     Fig. 4 (Sec. V.C): Si-9%As (k_e = 0.3, D_l = 1.5e-8 m^2/s, dT0 = 84 K) at
     W = 13.5 nm, D_s/D_l = 0.1, b = 1, G = 1.4e7 K/m (l_T = dT0 / G = 6 um =
@@ -166,14 +166,18 @@ def config_ti_curve(A: float, N: int = 2048, nruns: int = 24, steps: int = 60000
     ``nruns`` 1D runs with v_p log-spaced from 0.02 to 1 m/s (V = v_p W / D_l),
     N cells each, the front in mid-window (T_I moves it by up to a few
     hundred W), dt = min(0.2 dx^2, run_dt(V)), ``steps`` steps (about 1.7
-    thermal times l_T / V at 0.02 m/s).  Returns (base params, runs, steps,
-    v_p in m/s)."""
+    thermal times l_T / V at 0.02 m/s).  N = 0 and steps = 0 take 2048 cells
+    and 600000 steps at dx = 0.8, and the same window and time span at
+    another grid spacing dx.  Returns (base params, runs, steps, v_p in m/s)."""
     I0 = 1.0 / (3.0 * math.sqrt(2.0))
     ke = 0.3
+    N = N or int(round(2048 * DX / dx))
+    steps = steps or int(round(600000 * DX * DX / (dx * dx)))
     vp = np.geomspace(0.02, 1.0, nruns)
-    runs = [dict(N=N, V=float(v * 13.5e-9 / 1.5e-8), dt=float(min(0.2 * DX * DX, run_dt(v * 13.5e-9 / 1.5e-8))),
-                 z0=(N // 2) * DX) for v in vp]
-    base = base_params(dim=1)
+    runs = [dict(N=N, V=float(v * 13.5e-9 / 1.5e-8),
+                 dt=float(min(0.2 * dx * dx, run_dt(v * 13.5e-9 / 1.5e-8, dx=dx))), z0=(N // 2) * dx)
+            for v in vp]
+    base = base_params(dim=1, dx=dx)
     base.update(ke=ke, Ds=0.1, b=1.0, A=A, lambda0=I0 * ke / (1.0 - ke) ** 2, inv_lT=13.5e-9 * 1.4e7 / 84.0)
     return base, runs, steps, vp
 

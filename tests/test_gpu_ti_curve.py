@@ -44,3 +44,27 @@ def test_interface_temperature_rises_then_drops():
     assert T[fast].max() > T[0] + 0.15  # rises
     assert T[-1] < T[fast].max() - 0.3 and T[-1] < 0.0  # drops below the solidus at 1 m/s
     assert base["ke"] < k[0] < k[-1] < 1.0
+
+
+def test_band_oscillation_at_finer_grid():
+    """The oscillation at 0.11 m/s (A = 1.2) is not an effect of the coarse
+    grid: at dx = 0.5, with the same window and time span, the front speed
+    still swings by more than 20 % around V, without decay, over the last
+    third of the run."""
+    import torch
+    from paper_2303_09671_amd import pf
+    from paper_2303_09671_amd.front import front_series, front_state, oscillation
+    base, runs, steps, vp = I.config_ti_curve(1.2, dx=0.5)
+    r = [runs[10]]
+    assert abs(vp[10] - 0.11) < 0.005
+    every = 12500
+    print(f"case: T_I(V) run at {vp[10]:.3f} m/s, dx = 0.5, {steps} steps, front every {every}", flush=True)
+    phi, cs, cl, offs = I.batch_fields(r, ke=base["ke"])
+    t = [torch.from_numpy(a).cuda() for a in (phi, cs, cl)]
+    h = pf.pf_create(base, *t, runs=r, offsets=offs)
+    ser = front_series(h, steps, every, [r[0]["dt"]])
+    assert pf.pf_check(h) == pf.PF_OK
+    V, t_from = r[0]["V"], steps * r[0]["dt"] * 2.0 / 3.0
+    assert front_state(ser, 0, V, t_from) == "oscillating"
+    o = oscillation(ser, 0, t_from)
+    assert o["v_max"] > 1.2 * V and o["v_min"] < 0.8 * V
