@@ -174,24 +174,27 @@ def test_source_A_equals_one(torch_dev, oracle, dim):
     assert_parity(g, ref[:3], what=f"A=1 {dim}D")
 
 
-@pytest.mark.parametrize("dim,n", [(3, (64, 16, 40)), (3, (41, 13, 40)), (2, (150, 1, 60))])
-def test_ring_load_paths_agree(torch_dev, oracle, dim, n):
+@pytest.mark.parametrize("dim,n,model", [(3, (64, 16, 40), 0), (3, (41, 13, 40), 0), (2, (150, 1, 60), 0),
+                                         (3, (41, 13, 40), 1), (2, (150, 1, 60), 1)])
+def test_ring_load_paths_agree(torch_dev, oracle, dim, n, model):
     """The ring planes of the 2D/3D step go from global memory into LDS by DMA
     (16 bytes a lane) where two ring positions are adjacent and 16-byte aligned
     in memory, and through registers otherwise.  Fields passed as views 8 bytes
     off a 16-byte boundary take the register path on every step that reads
     them (the handle's twins stay aligned, so the steps alternate); odd nx and
     ny (41 x 13) put periodic wraps inside pairs and leave every other row and
-    plane misaligned.  Both runs must agree bit for bit and match the oracle."""
+    plane misaligned.  Both runs must agree bit for bit and match the oracle,
+    for both models (the equal-potential one loads no c_s)."""
     if dim == 3:
         p, _, pert = I.config_3d(n=8)
         p = dict(p, n=n, periodic=(1, 1, 0), V=0.6, z0=14 * I.DX)
     else:
         p, _, pert = I.config_2d(nx=n[0], nz=n[2])
         p = dict(p, periodic=(1, 0, 0), V=0.5, z0=14 * I.DX)
+    p = dict(p, model=model)
     f = [a.ravel() for a in I.planar_front(dim, p["n"], p["dx"], p["z0"], p["ke"], amp=0.05, seed=pert["seed"])]
     steps = 61
-    print(f"case: ring load paths {dim}D {n} steps={steps}", flush=True)
+    print(f"case: ring load paths {dim}D {n} model={model} steps={steps}", flush=True)
     from paper_2303_09671_amd import pf
     _, _, g_al = _run_gpu(torch_dev, p, f, steps)
     views = []
@@ -210,7 +213,7 @@ def test_ring_load_paths_agree(torch_dev, oracle, dim, n):
         assert np.array_equal(a, b)
     ref = oracle.step(oracle_params(oracle, p), *f, steps)
     assert ref[3] >= 1
-    assert_parity(g_al, ref[:3], what=f"ring load paths {dim}D {n}")
+    assert_parity(g_al, ref[:3], what=f"ring load paths {dim}D {n} model={model}")
 
 
 @pytest.mark.parametrize("which", ["2d", "3d"])
